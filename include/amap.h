@@ -1,0 +1,227 @@
+/*
+ * amap.h -- C ABI of the fast weak-lensing aperture-mass library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library implements the fast aperture-mass path of Leonard, Pires &
+ * Starck, "Fast Calculation of the Weak Lensing Aperture Mass Statistic"
+ * (arXiv:1204.4293): a pixelised shear map is turned into a convergence map
+ * by Kaiser-Squires inversion in Fourier space (Sec. 1, Sec. 4.5), the
+ * convergence map is decomposed by the starlet transform into J planes whose
+ * detail planes are aperture-mass maps at radii 2^j pixels (Sec. 3), noise
+ * maps come from randomising the shears many times and S = M_ap / sigma
+ * (Sec. 1), and peaks are counted per scale on S (Sec. 2.2).  The brute-force
+ * aperture mass of eq:shearmap is provided for comparison (Sec. 5.1).
+ *
+ * Conventions (all entry points):
+ *   - A map is square n x n, n a power of two with 16 <= n <= 4096, stored
+ *     row-major [y][x] with contiguous rows (x is the column index).  All
+ *     boundaries are periodic.
+ *   - J counts the planes produced *including* the smooth plane (Sec. 3:
+ *     J = j_max + 1), 2 <= J and 2^J <= n (Sec. 5.1).  A plane stack is
+ *     [J][n][n]: w_1 .. w_{J-1}, then c_{J-1}; w_j is the aperture-mass map
+ *     at theta = 2^j pixels.  Smoothing step j uses the B3-spline taps
+ *     (1,4,6,4,1)/16 at dilation 2^(j-1), row pass then column pass.
+ *   - Data pointers are DEVICE pointers, owned by the caller, of the element
+ *     type given by the dtype argument (float or double), 256-byte aligned.
+ *     The library reads or writes them only inside the work it enqueues and
+ *     keeps no reference after the call (plans: until amap_plan_destroy).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call validates its arguments on the host, enqueues its kernels on
+ *     `stream` and returns without waiting.  Work issued through one context
+ *     uses that context's workspace, so calls sharing a context must be
+ *     ordered on one stream (use one context per concurrent stream).
+ *   - Errors: a call returns a status; on failure nothing has been enqueued
+ *     and amap_last_error() describes the problem.  Asynchronous device
+ *     errors surface as AMAP_E_HIP from a later call or from amap_sync.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef AMAP_H
+#define AMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMAP_OK = 0,
+    AMAP_E_INVAL = 1,       /* invalid argument; nothing was enqueued        */
+    AMAP_E_NOMEM = 2,       /* device memory for workspace unavailable       */
+    AMAP_E_HIP = 3,         /* HIP runtime error (launch or asynchronous)    */
+    AMAP_E_UNSUPPORTED = 4  /* valid request this build does not handle      */
+} amap_status;
+
+typedef enum { AMAP_F32 = 0, AMAP_F64 = 1 } amap_dtype;
+
+/* Aperture-mass filters of Sec. 4: the starlet Q(eta) of Sec. 4.2, the
+ * polynomial S98 filter of eq:sch (fparam = l) and the Gaussian filter of
+ * eq:mexhat with A = 1 (fparam = b). */
+typedef enum {
+    AMAP_FILTER_STARLET = 0,
+    AMAP_FILTER_S98 = 1,
+    AMAP_FILTER_JBJ04 = 2
+} amap_filter;
+
+typedef struct amap_ctx*  amap_ctx_t;
+typedef struct amap_plan* amap_plan_t;
+
+/* Create a context on HIP device `hip_device`.  The context owns the
+ * twiddle tables and a growable device workspace.  *out is set on success. */
+amap_status amap_create(int hip_device, amap_ctx_t* out);
+
+/* Destroy a context after waiting for its device; NULL is accepted. */
+amap_status amap_destroy(amap_ctx_t ctx);
+
+/* Text of the last error of the calling thread ("" if none).  Valid until
+ * the next amap_* call on that thread. */
+const char* amap_last_error(void);
+
+/* Wait for `stream` and report any asynchronous device error. */
+amap_status amap_sync(amap_ctx_t ctx, void* stream);
+
+/* Bytes of workspace the context currently holds on the device. */
+size_t amap_workspace_bytes(amap_ctx_t ctx);
+
+/* Per-kernel timing (diagnostics): while enabled, every kernel the context
+ * launches is bracketed by two HIP events recorded on the launch's stream.
+ * Work captured into a batch plan's graph is not timed. */
+amap_status amap_timing_enable(amap_ctx_t ctx, int enable);
+
+/* Waits for the timed work and writes a JSON object
+ * {"kernel": [launches, total_ms], ...} into buf (len bytes, including the
+ * terminating NUL; AMAP_E_INVAL if it does not fit).  reset != 0 clears the
+ * totals afterwards. */
+amap_status amap_timing_read(amap_ctx_t ctx, char* buf, size_t len, int reset);
+
+/*
+ * Kaiser-Squires inversion (Sec. 1: the shear map is converted into a
+ * convergence map in Fourier space; Sec. 4.5).
+ *   kappa = F^-1[ conj(D) F(g1 + i g2) ],
+ *   D(k) = [(k1^2 - k2^2) + 2 i nu k1 k2] / |k|^2, D(0) = 0,
+ * with k1 along x, nu = 0 on the Nyquist row and column, 1 elsewhere.
+ * Inputs g1, g2: n*n each.  Outputs kappa_e = Re kappa (n*n) and, if not
+ * NULL, kappa_b = Im kappa (n*n).  Outputs may not alias inputs.
+ */
+amap_status amap_ks_invert(amap_ctx_t ctx, amap_dtype dt, int n,
+                           const void* g1, const void* g2,
+                           void* kappa_e, void* kappa_b, void* stream);
+
+/*
+ * Starlet decomposition (Sec. 3; eq:splinewl with the B3 spline of
+ * Sec. 4.2): planes[J][n][n] = w_1 .. w_{J-1}, c_{J-1}, with c_0 = kappa,
+ * c_j = column(row(c_{j-1})) at dilation 2^(j-1), w_j = c_{j-1} - c_j.
+ * kappa: n*n; planes: J*n*n; they may not overlap.
+ */
+amap_status amap_starlet_forward(amap_ctx_t ctx, amap_dtype dt, int n, int J,
+                                 const void* kappa, void* planes, void* stream);
+
+/* Exact inverse of the decomposition (Sec. 3): kappa_out = c_{J-1} + sum w_j.
+ * planes: J*n*n; kappa_out: n*n (may not overlap planes). */
+amap_status amap_starlet_reconstruct(amap_ctx_t ctx, amap_dtype dt, int n, int J,
+                                     const void* planes, void* kappa_out, void* stream);
+
+/*
+ * Brute-force aperture mass from the tangential shear (eq:shearmap; cost
+ * O(n^2 cut^2), Sec. 5.1):
+ *   M(x) = sum_{0 < |d|^2 <= cut^2} Q_theta(|d|) gamma_t(x + d; x),
+ *   gamma_t = -[g1 (dx^2 - dy^2) + g2 2 dx dy] / |d|^2,
+ * indices periodic, pixel area 1.  Q_theta(r) = Q(r/theta)/theta^2 for the
+ * starlet; S98 and JBJ04 as printed (they carry their own 1/theta^2).
+ * theta_px > 0.  cut_px <= 0 selects the natural support: 2 theta
+ * (starlet), theta (S98), 5 theta (JBJ04).  The cut radius must satisfy
+ * 2*floor(cut) + 1 <= n and cut <= 256.  The inclusion test |d|^2 <= cut^2
+ * is made in double precision.  map_out: n*n.
+ */
+amap_status amap_map_direct(amap_ctx_t ctx, amap_dtype dt, int n,
+                            const void* g1, const void* g2, double theta_px,
+                            amap_filter filter, double fparam, double cut_px,
+                            void* map_out, void* stream);
+
+/*
+ * Noise maps from randomised shears (Sec. 1; Sec. 5.1).  For realisation
+ * r = 0 .. n_real-1 every pixel's shear is rotated by beta = 2 pi u,
+ * gamma' = gamma exp(i beta), with u the Philox4x64-10 uniform of
+ * amap_phase_uniforms; gamma' goes through the same KS inversion and
+ * starlet transform as the signal.  Per pixel and scale:
+ *   sigma_j = sqrt( (sum_r w^2 - (sum_r w)^2 / R) / (R - 1) ),
+ * accumulated in double precision.  If snr is not NULL, planes_signal
+ * (J*n*n, the signal's planes) must be given and snr_j = w_j / sigma_j
+ * (0 where sigma_j = 0).  sigma, snr: (J-1)*n*n.  n_real >= 2.
+ */
+amap_status amap_noise_maps(amap_ctx_t ctx, amap_dtype dt, int n, int J,
+                            const void* g1, const void* g2, int n_real, uint64_t seed,
+                            const void* planes_signal, void* sigma, void* snr,
+                            void* stream);
+
+/*
+ * Peak counts (Sec. 2.2; Sec. 4.3): for each of the `nplanes` n x n planes
+ * of `snr`, counts_dev[p] = number of pixels with value > threshold and
+ * value > each of its 8 periodic neighbours (strict; comparisons in double
+ * on the plane's exact values; NaN is never a peak).  counts_dev: device
+ * array of nplanes long long, overwritten.
+ */
+amap_status amap_count_peaks(amap_ctx_t ctx, amap_dtype dt, int n, int nplanes,
+                             const void* snr, double threshold,
+                             long long* counts_dev, void* stream);
+
+/*
+ * The 32-bit Philox values behind the noise phases (Sec. 1 randomisation):
+ * Philox4x64-10 (Salmon et al. 2011) with key (seed, 0) and block counter
+ * (b, r, 0, 0); block b gives pixels 8b .. 8b+7 (pixel = y*n + x), each
+ * 64-bit word split low half then high half.  The phase uniform is
+ * (v >> 8) * 2^-24.  out_u32: device array of n*n uint32.
+ */
+amap_status amap_phase_uniforms(amap_ctx_t ctx, int n, uint64_t seed, uint64_t r,
+                                uint32_t* out_u32, void* stream);
+
+/*
+ * The whole path for one map: KS inversion, starlet planes, noise sigma from
+ * n_real randomised realisations, S/N and peak counts above `threshold`.
+ * kappa_e (n*n) and kappa_b (n*n) may be NULL; planes (J*n*n), sigma and snr
+ * ((J-1)*n*n) and peaks (J-1 long long, device) are required.
+ */
+amap_status amap_run_path(amap_ctx_t ctx, amap_dtype dt, int n, int J,
+                          const void* g1, const void* g2, int n_real, uint64_t seed,
+                          double threshold, void* kappa_e, void* kappa_b,
+                          void* planes, void* sigma, void* snr,
+                          long long* peaks, void* stream);
+
+/* ---- batched maps: one launch sequence over many maps of uneven sizes ---- */
+
+/* One map of a batch.  n_real == 0 runs KS + starlet only (sigma, snr,
+ * peaks ignored); n_real >= 2 runs the whole path as amap_run_path. */
+typedef struct {
+    int n, J, n_real;
+    uint64_t seed;
+    double threshold;
+    const void *g1, *g2;
+    void *kappa_e;      /* n*n or NULL                     */
+    void *planes;       /* J*n*n, required                 */
+    void *sigma, *snr;  /* (J-1)*n*n when n_real >= 2       */
+    long long* peaks;   /* J-1 device counts when n_real>=2 */
+} amap_job;
+
+/* Validate `jobs` and build a plan that runs all of them.  The plan owns its
+ * own workspace (independent of the context's) and a captured HIP graph per
+ * stream; it keeps the job pointers until destroyed. */
+amap_status amap_batch_plan(amap_ctx_t ctx, amap_dtype dt, const amap_job* jobs,
+                            int njobs, amap_plan_t* out);
+
+/* Run every job of the plan on `stream` (one graph launch after the first
+ * call on that stream). */
+amap_status amap_batch_run(amap_plan_t plan, void* stream);
+
+/* Destroy a plan after waiting for its work; NULL is accepted. */
+amap_status amap_plan_destroy(amap_plan_t plan);
+
+/* Device bytes a job needs besides its own inputs and outputs (the unit an
+ * admission policy budgets against). */
+size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMAP_H */

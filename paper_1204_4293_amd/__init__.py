@@ -1,0 +1,240 @@
+"""Python binding of the MI355X aperture-mass library (libamap.so).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors are PyTorch CUDA (ROCm) tensors, contiguous, float32 or
+float64; work is enqueued on torch's current stream.  The binding fails with
+an exception when the library has not been built or cannot be loaded -- it
+has no fallback.
+
+The names mirror the C ABI in include/amap.h.
+"""
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libamap.so")
+HEADER = os.path.join(ROOT, "include", "amap.h")
+
+F32, F64 = 0, 1
+FILTER_STARLET, FILTER_S98, FILTER_JBJ04 = 0, 1, 2
+_STATUS = {0: "AMAP_OK", 1: "AMAP_E_INVAL", 2: "AMAP_E_NOMEM", 3: "AMAP_E_HIP",
+           4: "AMAP_E_UNSUPPORTED"}
+
+_lib = None
+
+
+class AmapError(RuntimeError):
+    """A non-OK status from the library; ``status`` holds the code."""
+
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class AmapJob(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("J", ctypes.c_int), ("n_real", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("threshold", ctypes.c_double),
+                ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p),
+                ("kappa_e", ctypes.c_void_p), ("planes", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("snr", ctypes.c_void_p),
+                ("peaks", ctypes.c_void_p)]
+
+
+def header_symbols():
+    """Names of the functions include/amap.h declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(amap_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Load libamap.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libamap.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+    sig = {
+        "amap_create": (I, [I, ctypes.POINTER(P)]),
+        "amap_destroy": (I, [P]),
+        "amap_last_error": (ctypes.c_char_p, []),
+        "amap_sync": (I, [P, P]),
+        "amap_workspace_bytes": (ctypes.c_size_t, [P]),
+        "amap_timing_enable": (I, [P, I]),
+        "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
+        "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
+        "amap_starlet_forward": (I, [P, I, I, I, P, P, P]),
+        "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
+        "amap_map_direct": (I, [P, I, I, P, P, D, I, D, D, P, P]),
+        "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
+        "amap_count_peaks": (I, [P, I, I, I, P, D, P, P]),
+        "amap_phase_uniforms": (I, [P, I, U64, U64, P, P]),
+        "amap_run_path": (I, [P, I, I, I, P, P, I, U64, D, P, P, P, P, P, P, P]),
+        "amap_batch_plan": (I, [P, I, ctypes.POINTER(AmapJob), I, ctypes.POINTER(P)]),
+        "amap_batch_run": (I, [P, P]),
+        "amap_plan_destroy": (I, [P]),
+        "amap_job_footprint_bytes": (ctypes.c_size_t, [I, I, I, I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise AmapError(status, load().amap_last_error().decode())
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("tensors must be float32 or float64, got %s" % t.dtype)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _side(t):
+    n = t.shape[-1]
+    if t.shape[-2] != n:
+        raise ValueError("maps must be square")
+    return n
+
+
+def job_footprint_bytes(dtype, n, J, n_real):
+    return int(load().amap_job_footprint_bytes(dtype, n, J, n_real))
+
+
+class Context:
+    """A library context on one HIP device (owns twiddles and workspace)."""
+
+    def __init__(self, device=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.amap_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if self._h:
+            load().amap_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(load().amap_sync(self._h, _stream()))
+
+    def timing_enable(self, enable=True):
+        _check(load().amap_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self, reset=False):
+        """{kernel: (launches, total_ms)} of the HIP-event timer."""
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(load().amap_timing_read(self._h, buf, len(buf), 1 if reset else 0))
+        return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
+    def workspace_bytes(self):
+        return int(load().amap_workspace_bytes(self._h))
+
+    def _empty(self, shape, like):
+        return torch.empty(shape, dtype=like.dtype, device=like.device)
+
+    def ks_invert(self, g1, g2, kappa_e=None, kappa_b=None, want_b=False):
+        n = _side(g1)
+        kappa_e = self._empty((n, n), g1) if kappa_e is None else kappa_e
+        if kappa_b is None and want_b:
+            kappa_b = self._empty((n, n), g1)
+        _check(load().amap_ks_invert(self._h, _dt(g1), n, _ptr(g1), _ptr(g2), _ptr(kappa_e),
+                                     _ptr(kappa_b), _stream()))
+        return kappa_e, kappa_b
+
+    def starlet_forward(self, kappa, J, planes=None):
+        n = _side(kappa)
+        planes = self._empty((J, n, n), kappa) if planes is None else planes
+        _check(load().amap_starlet_forward(self._h, _dt(kappa), n, int(J), _ptr(kappa),
+                                           _ptr(planes), _stream()))
+        return planes
+
+    def starlet_reconstruct(self, planes, out=None):
+        J, n = planes.shape[0], _side(planes)
+        out = self._empty((n, n), planes) if out is None else out
+        _check(load().amap_starlet_reconstruct(self._h, _dt(planes), n, J, _ptr(planes),
+                                               _ptr(out), _stream()))
+        return out
+
+    def map_direct(self, g1, g2, theta, filter=FILTER_STARLET, fparam=0.0, cut=0.0, out=None):
+        n = _side(g1)
+        out = self._empty((n, n), g1) if out is None else out
+        _check(load().amap_map_direct(self._h, _dt(g1), n, _ptr(g1), _ptr(g2), float(theta),
+                                      int(filter), float(fparam), float(cut), _ptr(out), _stream()))
+        return out
+
+    def noise_maps(self, g1, g2, J, n_real, seed, planes_signal=None, sigma=None, snr=None,
+                   want_snr=True):
+        n = _side(g1)
+        sigma = self._empty((J - 1, n, n), g1) if sigma is None else sigma
+        if snr is None and want_snr and planes_signal is not None:
+            snr = self._empty((J - 1, n, n), g1)
+        _check(load().amap_noise_maps(self._h, _dt(g1), n, int(J), _ptr(g1), _ptr(g2),
+                                      int(n_real), int(seed), _ptr(planes_signal), _ptr(sigma),
+                                      _ptr(snr), _stream()))
+        return sigma, snr
+
+    def count_peaks(self, snr, threshold, counts=None):
+        nplanes, n = snr.shape[0], _side(snr)
+        counts = (torch.empty(nplanes, dtype=torch.int64, device=snr.device)
+                  if counts is None else counts)
+        _check(load().amap_count_peaks(self._h, _dt(snr), n, nplanes, _ptr(snr), float(threshold),
+                                       _ptr(counts), _stream()))
+        return counts
+
+    def phase_uniforms(self, n, seed, r, out=None):
+        out = torch.empty((n, n), dtype=torch.int32, device=self.device) if out is None else out
+        _check(load().amap_phase_uniforms(self._h, int(n), int(seed), int(r), _ptr(out), _stream()))
+        return out
+
+    def run_path(self, g1, g2, J, n_real, seed, threshold=3.0, out=None, want_kappa=True):
+        """The whole path; returns a dict of output tensors (allocated unless
+        given in ``out``)."""
+        n = _side(g1)
+        o = dict(out or {})
+        if want_kappa:
+            o.setdefault("kappa_e", self._empty((n, n), g1))
+        o.setdefault("planes", self._empty((J, n, n), g1))
+        o.setdefault("sigma", self._empty((J - 1, n, n), g1))
+        o.setdefault("snr", self._empty((J - 1, n, n), g1))
+        o.setdefault("peaks", torch.empty(J - 1, dtype=torch.int64, device=g1.device))
+        _check(load().amap_run_path(self._h, _dt(g1), n, int(J), _ptr(g1), _ptr(g2), int(n_real),
+                                    int(seed), float(threshold), _ptr(o.get("kappa_e")),
+                                    _ptr(o.get("kappa_b")), _ptr(o["planes"]), _ptr(o["sigma"]),
+                                    _ptr(o["snr"]), _ptr(o["peaks"]), _stream()))
+        return o

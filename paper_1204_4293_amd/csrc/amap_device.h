@@ -1,0 +1,89 @@
+// Device-side building blocks shared by the kernels of the library:
+// a small complex type, the Philox4x64-10 counter-based generator, and the
+// periodic-index helpers.  Written for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amap {
+
+constexpr int kMaxLogN = 12;          // largest map side 4096
+constexpr int kMaxN = 1 << kMaxLogN;
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> make_cpx(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return make_cpx(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return make_cpx(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return make_cpx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// multiply by the conjugate of b
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+    return make_cpx(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> rot90(cpx<T> a) {
+    return INV ? make_cpx(-a.y, a.x) : make_cpx(a.y, -a.x);
+}
+
+// ---- Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11) ----------------
+struct u64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                               uint64_t c3, uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    u64x4 r;
+    r.v[0] = c0; r.v[1] = c1; r.v[2] = c2; r.v[3] = c3;
+    return r;
+}
+
+// The eight 32-bit values of block b (pixels 8b .. 8b+7) of realisation r.
+__device__ __forceinline__ void philox_block_u32(uint64_t seed, uint64_t r, uint64_t b,
+                                                 uint32_t out[8]) {
+    const u64x4 w = philox4x64_10(b, r, 0, 0, seed, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        out[2 * i] = (uint32_t)(w.v[i] & 0xFFFFFFFFull);
+        out[2 * i + 1] = (uint32_t)(w.v[i] >> 32);
+    }
+}
+
+// Rotation of a shear value by beta = 2 pi u, u = (v >> 8) 2^-24.
+__device__ __forceinline__ void rotate_by_u32(uint32_t v, float& a, float& b) {
+    const float u2 = (float)(v >> 8) * (1.0f / 8388608.0f);  // 2u, exact
+    float s, c;
+    sincospif(u2, &s, &c);
+    const float na = a * c - b * s;
+    const float nb = a * s + b * c;
+    a = na; b = nb;
+}
+__device__ __forceinline__ void rotate_by_u32(uint32_t v, double& a, double& b) {
+    const double u2 = (double)(v >> 8) * (1.0 / 8388608.0);
+    double s, c;
+    sincospi(u2, &s, &c);
+    const double na = a * c - b * s;
+    const double nb = a * s + b * c;
+    a = na; b = nb;
+}
+
+}  // namespace amap

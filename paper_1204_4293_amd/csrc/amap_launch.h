@@ -1,0 +1,97 @@
+// Host-side launchers of the library's kernels (internal to the library).
+// Each launcher enqueues on `stream` and returns hipGetLastError().
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amap {
+
+template <typename T> struct cpx;
+
+// Optional per-kernel timing.  When a KernelTimer is installed for the
+// calling thread, every launch is bracketed by HIP events recorded on the
+// launch's own stream.
+struct KernelTimer {
+    virtual ~KernelTimer() {}
+    virtual void begin(const char* name, hipStream_t s) = 0;
+    virtual void end(hipStream_t s) = 0;
+};
+KernelTimer*& current_timer();
+
+#define AMAP_LAUNCH(name, stream, ...)                         \
+    do {                                                       \
+        ::amap::KernelTimer* t_ = ::amap::current_timer();     \
+        if (t_) t_->begin(name, stream);                       \
+        __VA_ARGS__;                                           \
+        if (t_) t_->end(stream);                               \
+    } while (0)
+
+// Kaiser-Squires inversion of `batch` maps of side 2^logn.
+//   g1/g2:   map b at g + b*g_stride (g_stride = 0: one map, many realisations)
+//   C:       complex workspace, batch*n*n
+//   kE/kB:   outputs at + b*out_stride; kB may be null
+//   rotate:  rotate pixel shears by the Philox phases of realisation r0 + b
+template <typename T>
+struct KsArgs {
+    int logn;
+    int batch;
+    const T* g1;
+    const T* g2;
+    long long g_stride;
+    cpx<T>* C;
+    T* kE;
+    T* kB;
+    long long out_stride;
+    bool rotate;
+    uint64_t seed;
+    uint64_t r0;
+    const cpx<T>* tw;  // exp(-2 pi i k / 4096), k < 4096
+    hipStream_t stream;
+};
+template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
+
+// Starlet decomposition of `batch` maps: kappa at + b*in_stride, planes at
+// + b*planes_stride (J planes of n*n), tmp: batch*n*n scratch.
+template <typename T>
+struct StarletArgs {
+    int logn, J, batch;
+    const T* kappa;
+    long long in_stride;
+    T* planes;
+    long long planes_stride;
+    T* tmp;
+    hipStream_t stream;
+};
+template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
+template <typename T>
+hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStream_t s);
+
+// Noise statistics.
+//   accumulate: S1[j] += sum_b w_{b,j}, S2[j] += sum_b w_{b,j}^2 over `batch`
+//   realisations whose planes sit at planes + b*planes_stride (j < J-1)
+template <typename T>
+hipError_t launch_noise_accumulate(int logn, int J, int batch, const T* planes,
+                                   long long planes_stride, double* S1, double* S2,
+                                   hipStream_t s);
+// sigma = sqrt((S2 - S1^2/R)/(R-1)); snr = w/sigma (0 where sigma = 0) if snr
+template <typename T>
+hipError_t launch_noise_finalize(int logn, int J, int R, const double* S1, const double* S2,
+                                 const T* planes_signal, T* sigma, T* snr, hipStream_t s);
+hipError_t launch_zero_f64(double* p, long long count, hipStream_t s);
+hipError_t launch_zero_i64(long long* p, long long count, hipStream_t s);
+
+template <typename T>
+hipError_t launch_count_peaks(int logn, int nplanes, const T* snr, double thr,
+                              long long* counts, hipStream_t s);
+
+hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, hipStream_t s);
+
+// Direct aperture mass: taps for offsets dy in [-R, R] (row dy + R), the
+// dx range [-half[dy+R], half[dy+R]] (half < 0: empty row), weights wc
+// (Q cos 2phi) and ws (Q sin 2phi) dense [(2R+1)][(2R+1)] in T.
+template <typename T>
+hipError_t launch_map_direct(int logn, const T* g1, const T* g2, int R, const int* half,
+                             const T* wc, const T* ws, T* out, hipStream_t s);
+
+}  // namespace amap

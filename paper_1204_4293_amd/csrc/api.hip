@@ -1,0 +1,857 @@
+// C ABI of the aperture-mass library (declared in include/amap.h): argument
+// validation, contexts, device workspace, filter tables for the direct sum,
+// and the sequencing of the kernels of each entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amap.h"
+#include "amap_device.h"
+#include "amap_launch.h"
+#include "amap_host.h"
+
+using namespace amap;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+amap_status fail(amap_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+amap_status hip_fail(hipError_t e, const char* what) {
+    return fail(AMAP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the context's device current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(long long v) { int l = 0; while ((1ll << l) < v) ++l; return l; }
+
+amap_status check_n(int n) {
+    if (n < 16 || n > 4096 || !is_pow2(n))
+        return fail(AMAP_E_INVAL, "n must be a power of two in [16, 4096] (got %d)", n);
+    return AMAP_OK;
+}
+amap_status check_J(int n, int J) {
+    if (J < 2) return fail(AMAP_E_INVAL, "J must be >= 2 (got %d)", J);
+    if (J > 30 || (1ll << J) > n)
+        return fail(AMAP_E_INVAL, "2^J must not exceed n (J=%d, n=%d)", J, n);
+    return AMAP_OK;
+}
+amap_status check_ptr(const void* p, const char* name, bool required = true) {
+    if (!p) return required ? fail(AMAP_E_INVAL, "%s must not be NULL", name) : AMAP_OK;
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0)
+        return fail(AMAP_E_INVAL, "%s must be 256-byte aligned", name);
+    return AMAP_OK;
+}
+amap_status check_dtype(amap_dtype dt) {
+    if (dt != AMAP_F32 && dt != AMAP_F64) return fail(AMAP_E_INVAL, "unknown dtype %d", (int)dt);
+    return AMAP_OK;
+}
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+size_t esize(amap_dtype dt) { return dt == AMAP_F64 ? 8 : 4; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+#define AMAP_TRY(expr)                           \
+    do {                                         \
+        amap_status s_ = (expr);                 \
+        if (s_ != AMAP_OK) return s_;            \
+    } while (0)
+#define AMAP_HIP(expr, what)                     \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+}  // namespace
+
+namespace amap {
+KernelTimer*& current_timer() {
+    static thread_local KernelTimer* t = nullptr;
+    return t;
+}
+}  // namespace amap
+
+// Per-kernel timing with HIP events recorded on each launch's stream.
+struct EventTimer : KernelTimer {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<long long, double>> totals;  // launches, ms
+
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    void begin(const char* name, hipStream_t s) override {
+        Rec r{name, get(), get()};
+        if (r.a) (void)hipEventRecord(r.a, s);
+        pending.push_back(r);
+    }
+    void end(hipStream_t s) override {
+        if (!pending.empty() && pending.back().b) (void)hipEventRecord(pending.back().b, s);
+    }
+    void flush() {
+        for (Rec& r : pending) {
+            float ms = 0.f;
+            if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess &&
+                hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto& t = totals[r.name];
+                t.first += 1;
+                t.second += ms;
+            }
+            if (r.a) pool.push_back(r.a);
+            if (r.b) pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~EventTimer() override {
+        flush();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct amap_ctx {
+    int device = 0;
+    cpx<float>* tw32 = nullptr;
+    cpx<double>* tw64 = nullptr;
+    Workspace ws;
+    EventTimer* timer = nullptr;
+};
+
+namespace {
+// Installs the context's timer (if any) for the calling thread.
+struct TimerScope {
+    KernelTimer* prev;
+    explicit TimerScope(const amap_ctx* c) : prev(current_timer()) {
+        current_timer() = c ? c->timer : nullptr;
+    }
+    ~TimerScope() { current_timer() = prev; }
+};
+}  // namespace
+
+// ---- workspace ---------------------------------------------------------------------
+amap_status Workspace::reserve(size_t bytes) {
+    if (bytes <= size) return AMAP_OK;
+    if (ptr) {
+        // earlier work may still use the old buffer
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "device synchronize before workspace growth");
+        (void)hipFree(ptr);
+        ptr = nullptr;
+        size = 0;
+    }
+    const size_t want = align256(bytes);
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+        return fail(AMAP_E_NOMEM, "cannot allocate %zu bytes of device workspace", want);
+    }
+    size = want;
+    return AMAP_OK;
+}
+void Workspace::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    size = 0;
+}
+
+// ---- twiddles ----------------------------------------------------------------------
+// exp(-2 pi i k / 4096), evaluated in long double and rounded once.
+template <typename T>
+static amap_status upload_twiddles(cpx<T>** out) {
+    std::vector<T> host(2 * kMaxN);
+    for (int k = 0; k < kMaxN; ++k) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / kMaxN;
+        host[2 * k] = (T)cosl(a);
+        host[2 * k + 1] = (T)sinl(a);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, host.size() * sizeof(T)) != hipSuccess)
+        return fail(AMAP_E_NOMEM, "cannot allocate twiddle table");
+    if (hipMemcpy(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);
+        return fail(AMAP_E_HIP, "cannot upload twiddle table");
+    }
+    *out = static_cast<cpx<T>*>(p);
+    return AMAP_OK;
+}
+
+template <typename T> const cpx<T>* twiddles(const amap_ctx* c);
+template <> const cpx<float>* twiddles<float>(const amap_ctx* c) { return c->tw32; }
+template <> const cpx<double>* twiddles<double>(const amap_ctx* c) { return c->tw64; }
+
+// ---- direct-sum tap table ----------------------------------------------------------------
+static amap_status build_tap_table(amap_filter f, double theta, double fparam, double cut_px,
+                                   int n, TapTable* t) {
+    double cut = cut_px;
+    if (!(cut > 0.0)) {
+        cut = f == AMAP_FILTER_STARLET ? 2.0 * theta : (f == AMAP_FILTER_S98 ? theta : 5.0 * theta);
+    }
+    if (!std::isfinite(cut) || cut > 256.0)
+        return fail(AMAP_E_INVAL, "cut radius %g exceeds the supported 256 px", cut);
+    const int R = (int)std::floor(cut);
+    if (2 * R + 1 > n)
+        return fail(AMAP_E_INVAL, "cut radius %g too large for n = %d (need 2*floor(cut)+1 <= n)",
+                    cut, n);
+    const double c2 = cut * cut;
+    const int D = 2 * R + 1;
+    t->R = R;
+    t->half.assign(D, -1);
+    t->wc.assign((size_t)D * D, 0.0);
+    t->ws.assign((size_t)D * D, 0.0);
+    for (int dy = -R; dy <= R; ++dy) {
+        for (int dx = -R; dx <= R; ++dx) {
+            const double r2 = (double)(dx * dx + dy * dy);
+            if (r2 > c2) continue;
+            const int ax = dx < 0 ? -dx : dx;
+            if (ax > t->half[dy + R]) t->half[dy + R] = ax;
+            if (r2 == 0.0) continue;
+            const double r = std::sqrt(r2);
+            double q;
+            if (f == AMAP_FILTER_STARLET) q = starlet_Q(r / theta) / (theta * theta);
+            else if (f == AMAP_FILTER_S98) q = s98_Q(r, theta, fparam);
+            else q = jbj04_Q(r, theta, fparam);
+            const size_t i = (size_t)(dy + R) * D + (dx + R);
+            t->wc[i] = q * (double)(dx * dx - dy * dy) / r2;
+            t->ws[i] = q * 2.0 * (double)dx * (double)dy / r2;
+        }
+    }
+    return AMAP_OK;
+}
+
+// ---- path pieces (typed) -------------------------------------------------------------
+namespace amap {
+
+template <typename T>
+amap_status enqueue_ks(const amap_ctx* ctx, int logn, int batch, const T* g1, const T* g2,
+                       long long g_stride, cpx<T>* C, T* kE, T* kB, long long out_stride,
+                       bool rotate, uint64_t seed, uint64_t r0, hipStream_t s) {
+    KsArgs<T> a;
+    a.logn = logn; a.batch = batch; a.g1 = g1; a.g2 = g2; a.g_stride = g_stride; a.C = C;
+    a.kE = kE; a.kB = kB; a.out_stride = out_stride; a.rotate = rotate; a.seed = seed;
+    a.r0 = r0; a.tw = twiddles<T>(ctx); a.stream = s;
+    AMAP_HIP(launch_ks<T>(a), "KS kernels");
+    return AMAP_OK;
+}
+
+template <typename T>
+amap_status enqueue_starlet(int logn, int J, int batch, const T* kappa, long long in_stride,
+                            T* planes, long long planes_stride, T* tmp, hipStream_t s) {
+    StarletArgs<T> a;
+    a.logn = logn; a.J = J; a.batch = batch; a.kappa = kappa; a.in_stride = in_stride;
+    a.planes = planes; a.planes_stride = planes_stride; a.tmp = tmp; a.stream = s;
+    AMAP_HIP(launch_starlet<T>(a), "starlet kernels");
+    return AMAP_OK;
+}
+
+// Realisations per launch sequence of the noise loop.
+int noise_batch(int n, int n_real) {
+    const long long n2 = (long long)n * n;
+    long long b = (1ll << 24) / n2;  // ~16 M pixels of realisations in flight
+    if (b < 1) b = 1;
+    if (b > n_real) b = n_real;
+    return (int)b;
+}
+
+size_t noise_workspace_bytes(amap_dtype dt, int n, int J, int n_real) {
+    const size_t n2 = (size_t)n * n, e = esize(dt);
+    const size_t B = (size_t)noise_batch(n, n_real);
+    return align256(B * n2 * 2 * e)            // complex spectra
+         + align256(B * n2 * e)                // kappa of each realisation
+         + align256(B * n2 * (size_t)J * e)    // planes of each realisation
+         + align256(B * n2 * e)                // starlet row-pass scratch
+         + 2 * align256((size_t)(J - 1) * n2 * 8);  // S1, S2
+}
+
+template <typename T>
+amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* g1,
+                          const T* g2, int n_real, uint64_t seed, const T* planes_signal,
+                          T* sigma, T* snr, hipStream_t s) {
+    const int logn = ilog2(n);
+    const long long n2 = (long long)n * n;
+    const int B = noise_batch(n, n_real);
+    char* p = ws;
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(p);   p += align256((size_t)B * n2 * 2 * sizeof(T));
+    T* kap = reinterpret_cast<T*>(p);            p += align256((size_t)B * n2 * sizeof(T));
+    T* planes = reinterpret_cast<T*>(p);         p += align256((size_t)B * n2 * J * sizeof(T));
+    T* tmp = reinterpret_cast<T*>(p);            p += align256((size_t)B * n2 * sizeof(T));
+    double* S1 = reinterpret_cast<double*>(p);   p += align256((size_t)(J - 1) * n2 * 8);
+    double* S2 = reinterpret_cast<double*>(p);
+    AMAP_HIP(launch_zero_f64(S1, (long long)(J - 1) * n2, s), "zero accumulators");
+    AMAP_HIP(launch_zero_f64(S2, (long long)(J - 1) * n2, s), "zero accumulators");
+    for (int r0 = 0; r0 < n_real; r0 += B) {
+        const int bb = (n_real - r0) < B ? (n_real - r0) : B;
+        AMAP_TRY(enqueue_ks<T>(ctx, logn, bb, g1, g2, 0, C, kap, nullptr, n2, true, seed,
+                               (uint64_t)r0, s));
+        AMAP_TRY(enqueue_starlet<T>(logn, J, bb, kap, n2, planes, (long long)J * n2, tmp, s));
+        AMAP_HIP(launch_noise_accumulate<T>(logn, J, bb, planes, (long long)J * n2, S1, S2, s),
+                 "noise accumulation");
+    }
+    AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, S1, S2, planes_signal, sigma, snr, s),
+             "noise finalize");
+    return AMAP_OK;
+}
+
+}  // namespace amap
+
+// ---- C ABI -------------------------------------------------------------------------------
+extern "C" {
+
+const char* amap_last_error(void) { return g_last_error.c_str(); }
+
+amap_status amap_create(int hip_device, amap_ctx_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(AMAP_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(AMAP_E_HIP, "no HIP device available");
+    if (hip_device < 0 || hip_device >= count)
+        return fail(AMAP_E_INVAL, "device %d out of range (have %d)", hip_device, count);
+    DeviceGuard g(hip_device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", hip_device);
+    amap_ctx* c = new (std::nothrow) amap_ctx;
+    if (!c) return fail(AMAP_E_NOMEM, "out of host memory");
+    c->device = hip_device;
+    amap_status s = upload_twiddles<float>(&c->tw32);
+    if (s == AMAP_OK) s = upload_twiddles<double>(&c->tw64);
+    if (s != AMAP_OK) {
+        if (c->tw32) (void)hipFree(c->tw32);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return AMAP_OK;
+}
+
+amap_status amap_destroy(amap_ctx_t c) {
+    g_last_error.clear();
+    if (!c) return AMAP_OK;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    delete c->timer;
+    c->timer = nullptr;
+    c->ws.release();
+    if (c->tw32) (void)hipFree(c->tw32);
+    if (c->tw64) (void)hipFree(c->tw64);
+    delete c;
+    return AMAP_OK;
+}
+
+amap_status amap_sync(amap_ctx_t c, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    DeviceGuard g(c->device);
+    AMAP_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "stream synchronize");
+    AMAP_HIP(hipGetLastError(), "asynchronous error");
+    return AMAP_OK;
+}
+
+size_t amap_workspace_bytes(amap_ctx_t c) { return c ? c->ws.size : 0; }
+
+amap_status amap_timing_enable(amap_ctx_t c, int enable) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    DeviceGuard g(c->device);
+    if (enable && !c->timer) {
+        c->timer = new (std::nothrow) EventTimer;
+        if (!c->timer) return fail(AMAP_E_NOMEM, "out of host memory");
+    } else if (!enable && c->timer) {
+        delete c->timer;
+        c->timer = nullptr;
+    }
+    return AMAP_OK;
+}
+
+amap_status amap_timing_read(amap_ctx_t c, char* buf, size_t len, int reset) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!buf || len == 0) return fail(AMAP_E_INVAL, "buf must not be NULL");
+    std::string out = "{";
+    if (c->timer) {
+        DeviceGuard g(c->device);
+        c->timer->flush();
+        bool first = true;
+        for (const auto& kv : c->timer->totals) {
+            char item[256];
+            snprintf(item, sizeof item, "%s\"%s\": [%lld, %.6f]", first ? "" : ", ",
+                     kv.first.c_str(), kv.second.first, kv.second.second);
+            out += item;
+            first = false;
+        }
+        if (reset) c->timer->totals.clear();
+    }
+    out += "}";
+    if (out.size() + 1 > len) {
+        buf[0] = 0;
+        return fail(AMAP_E_INVAL, "buffer too small: need %zu bytes", out.size() + 1);
+    }
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return AMAP_OK;
+}
+
+amap_status amap_ks_invert(amap_ctx_t c, amap_dtype dt, int n, const void* g1, const void* g2,
+                           void* kappa_e, void* kappa_b, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(kappa_e, "kappa_e"));
+    AMAP_TRY(check_ptr(kappa_b, "kappa_b", false));
+    const size_t bytes = (size_t)n * n * esize(dt);
+    if (overlaps(kappa_e, bytes, g1, bytes) || overlaps(kappa_e, bytes, g2, bytes) ||
+        overlaps(kappa_b, bytes, g1, bytes) || overlaps(kappa_b, bytes, g2, bytes) ||
+        overlaps(kappa_e, bytes, kappa_b, bytes))
+        return fail(AMAP_E_INVAL, "outputs may not overlap inputs or each other");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_TRY(c->ws.reserve(2 * bytes));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    if (dt == AMAP_F32)
+        return enqueue_ks<float>(c, logn, 1, (const float*)g1, (const float*)g2, 0,
+                                 (cpx<float>*)c->ws.ptr, (float*)kappa_e, (float*)kappa_b,
+                                 (long long)n * n, false, 0, 0, s);
+    return enqueue_ks<double>(c, logn, 1, (const double*)g1, (const double*)g2, 0,
+                              (cpx<double>*)c->ws.ptr, (double*)kappa_e, (double*)kappa_b,
+                              (long long)n * n, false, 0, 0, s);
+}
+
+amap_status amap_starlet_forward(amap_ctx_t c, amap_dtype dt, int n, int J, const void* kappa,
+                                 void* planes, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_J(n, J));
+    AMAP_TRY(check_ptr(kappa, "kappa"));
+    AMAP_TRY(check_ptr(planes, "planes"));
+    const size_t plane = (size_t)n * n * esize(dt);
+    if (overlaps(kappa, plane, planes, plane * J))
+        return fail(AMAP_E_INVAL, "planes may not overlap kappa");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_TRY(c->ws.reserve(plane));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    const long long n2 = (long long)n * n;
+    if (dt == AMAP_F32)
+        return enqueue_starlet<float>(logn, J, 1, (const float*)kappa, n2, (float*)planes,
+                                      (long long)J * n2, (float*)c->ws.ptr, s);
+    return enqueue_starlet<double>(logn, J, 1, (const double*)kappa, n2, (double*)planes,
+                                   (long long)J * n2, (double*)c->ws.ptr, s);
+}
+
+amap_status amap_starlet_reconstruct(amap_ctx_t c, amap_dtype dt, int n, int J,
+                                     const void* planes, void* kappa_out, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_J(n, J));
+    AMAP_TRY(check_ptr(planes, "planes"));
+    AMAP_TRY(check_ptr(kappa_out, "kappa_out"));
+    const size_t plane = (size_t)n * n * esize(dt);
+    if (overlaps(kappa_out, plane, planes, plane * J))
+        return fail(AMAP_E_INVAL, "kappa_out may not overlap planes");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    hipError_t e = dt == AMAP_F32
+        ? launch_reconstruct<float>(logn, J, (const float*)planes, (float*)kappa_out, s)
+        : launch_reconstruct<double>(logn, J, (const double*)planes, (double*)kappa_out, s);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct kernel");
+    return AMAP_OK;
+}
+
+amap_status amap_map_direct(amap_ctx_t c, amap_dtype dt, int n, const void* g1, const void* g2,
+                            double theta_px, amap_filter filter, double fparam, double cut_px,
+                            void* map_out, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(map_out, "map_out"));
+    if (!(theta_px > 0.0) || !std::isfinite(theta_px))
+        return fail(AMAP_E_INVAL, "theta_px must be positive and finite");
+    if (filter != AMAP_FILTER_STARLET && filter != AMAP_FILTER_S98 && filter != AMAP_FILTER_JBJ04)
+        return fail(AMAP_E_INVAL, "unknown filter %d", (int)filter);
+    if (filter == AMAP_FILTER_S98 && !(fparam >= 0.0))
+        return fail(AMAP_E_INVAL, "S98 needs fparam = l >= 0");
+    if (filter == AMAP_FILTER_JBJ04 && !(fparam > 0.0))
+        return fail(AMAP_E_INVAL, "JBJ04 needs fparam = b > 0");
+    const size_t bytes = (size_t)n * n * esize(dt);
+    if (overlaps(map_out, bytes, g1, bytes) || overlaps(map_out, bytes, g2, bytes))
+        return fail(AMAP_E_INVAL, "map_out may not overlap the inputs");
+    TapTable tab;
+    AMAP_TRY(build_tap_table(filter, theta_px, fparam, cut_px, n, &tab));
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    const int D = 2 * tab.R + 1;
+    const size_t e = esize(dt);
+    const size_t off_w = align256((size_t)D * sizeof(int));
+    const size_t need = off_w + 2 * align256((size_t)D * D * e);
+    AMAP_TRY(c->ws.reserve(need));
+    char* base = static_cast<char*>(c->ws.ptr);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // The tables are staged synchronously: the workspace may still be read by
+    // earlier work on this stream, so wait for it first.
+    AMAP_HIP(hipStreamSynchronize(s), "stream synchronize before table upload");
+    AMAP_HIP(hipMemcpy(base, tab.half.data(), (size_t)D * sizeof(int), hipMemcpyHostToDevice),
+             "upload tap rows");
+    const int logn = ilog2(n);
+    if (dt == AMAP_F32) {
+        std::vector<float> wc(tab.wc.begin(), tab.wc.end()), ws(tab.ws.begin(), tab.ws.end());
+        char* pc = base + off_w;
+        char* ps = pc + align256((size_t)D * D * 4);
+        AMAP_HIP(hipMemcpy(pc, wc.data(), wc.size() * 4, hipMemcpyHostToDevice), "upload taps");
+        AMAP_HIP(hipMemcpy(ps, ws.data(), ws.size() * 4, hipMemcpyHostToDevice), "upload taps");
+        AMAP_HIP(launch_map_direct<float>(logn, (const float*)g1, (const float*)g2, tab.R,
+                                          (const int*)base, (const float*)pc, (const float*)ps,
+                                          (float*)map_out, s), "direct aperture-mass kernel");
+    } else {
+        char* pc = base + off_w;
+        char* ps = pc + align256((size_t)D * D * 8);
+        AMAP_HIP(hipMemcpy(pc, tab.wc.data(), tab.wc.size() * 8, hipMemcpyHostToDevice), "upload taps");
+        AMAP_HIP(hipMemcpy(ps, tab.ws.data(), tab.ws.size() * 8, hipMemcpyHostToDevice), "upload taps");
+        AMAP_HIP(launch_map_direct<double>(logn, (const double*)g1, (const double*)g2, tab.R,
+                                           (const int*)base, (const double*)pc, (const double*)ps,
+                                           (double*)map_out, s), "direct aperture-mass kernel");
+    }
+    return AMAP_OK;
+}
+
+static amap_status validate_noise(amap_dtype dt, int n, int J, const void* g1, const void* g2,
+                                  int n_real, const void* planes_signal, const void* sigma,
+                                  const void* snr) {
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_J(n, J));
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(sigma, "sigma"));
+    AMAP_TRY(check_ptr(snr, "snr", false));
+    AMAP_TRY(check_ptr(planes_signal, "planes_signal", snr != nullptr));
+    if (n_real < 2) return fail(AMAP_E_INVAL, "n_real must be >= 2 (got %d)", n_real);
+    const size_t plane = (size_t)n * n * esize(dt);
+    const size_t stack = plane * (size_t)(J - 1);
+    if (overlaps(sigma, stack, g1, plane) || overlaps(sigma, stack, g2, plane) ||
+        overlaps(snr, stack, g1, plane) || overlaps(snr, stack, g2, plane) ||
+        overlaps(sigma, stack, snr, stack) || overlaps(sigma, stack, planes_signal, plane * J) ||
+        overlaps(snr, stack, planes_signal, plane * J))
+        return fail(AMAP_E_INVAL, "sigma/snr may not overlap inputs or each other");
+    return AMAP_OK;
+}
+
+amap_status amap_noise_maps(amap_ctx_t c, amap_dtype dt, int n, int J, const void* g1,
+                            const void* g2, int n_real, uint64_t seed, const void* planes_signal,
+                            void* sigma, void* snr, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(validate_noise(dt, n, J, g1, g2, n_real, planes_signal, sigma, snr));
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_TRY(c->ws.reserve(noise_workspace_bytes(dt, n, J, n_real)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(c->ws.ptr);
+    if (dt == AMAP_F32)
+        return enqueue_noise<float>(c, ws, n, J, (const float*)g1, (const float*)g2, n_real, seed,
+                                    (const float*)planes_signal, (float*)sigma, (float*)snr, s);
+    return enqueue_noise<double>(c, ws, n, J, (const double*)g1, (const double*)g2, n_real, seed,
+                                 (const double*)planes_signal, (double*)sigma, (double*)snr, s);
+}
+
+amap_status amap_count_peaks(amap_ctx_t c, amap_dtype dt, int n, int nplanes, const void* snr,
+                             double threshold, long long* counts_dev, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    if (nplanes < 1 || nplanes > 65535) return fail(AMAP_E_INVAL, "nplanes must be in [1, 65535]");
+    AMAP_TRY(check_ptr(snr, "snr"));
+    if (!counts_dev) return fail(AMAP_E_INVAL, "counts_dev must not be NULL");
+    if (reinterpret_cast<uintptr_t>(counts_dev) % 8 != 0)
+        return fail(AMAP_E_INVAL, "counts_dev must be 8-byte aligned");
+    if (std::isnan(threshold)) return fail(AMAP_E_INVAL, "threshold must not be NaN");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    hipError_t e = dt == AMAP_F32
+        ? launch_count_peaks<float>(logn, nplanes, (const float*)snr, threshold, counts_dev, s)
+        : launch_count_peaks<double>(logn, nplanes, (const double*)snr, threshold, counts_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "peak kernel");
+    return AMAP_OK;
+}
+
+amap_status amap_phase_uniforms(amap_ctx_t c, int n, uint64_t seed, uint64_t r, uint32_t* out_u32,
+                                void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_ptr(out_u32, "out_u32"));
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_HIP(launch_phase_u32(ilog2(n), seed, r, out_u32, static_cast<hipStream_t>(stream)),
+             "phase kernel");
+    return AMAP_OK;
+}
+
+static amap_status validate_job(amap_dtype dt, const amap_job& j) {
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(j.n));
+    AMAP_TRY(check_J(j.n, j.J));
+    AMAP_TRY(check_ptr(j.g1, "g1"));
+    AMAP_TRY(check_ptr(j.g2, "g2"));
+    AMAP_TRY(check_ptr(j.planes, "planes"));
+    AMAP_TRY(check_ptr(j.kappa_e, "kappa_e", false));
+    const size_t plane = (size_t)j.n * j.n * esize(dt);
+    if (overlaps(j.planes, plane * j.J, j.g1, plane) || overlaps(j.planes, plane * j.J, j.g2, plane) ||
+        overlaps(j.kappa_e, plane, j.planes, plane * j.J) || overlaps(j.kappa_e, plane, j.g1, plane) ||
+        overlaps(j.kappa_e, plane, j.g2, plane))
+        return fail(AMAP_E_INVAL, "outputs may not overlap inputs or each other");
+    if (j.n_real == 0) return AMAP_OK;
+    AMAP_TRY(check_ptr(j.snr, "snr"));
+    AMAP_TRY(validate_noise(dt, j.n, j.J, j.g1, j.g2, j.n_real, j.planes, j.sigma, j.snr));
+    if (!j.peaks || reinterpret_cast<uintptr_t>(j.peaks) % 8 != 0)
+        return fail(AMAP_E_INVAL, "peaks must be a non-NULL 8-byte aligned device pointer");
+    if (std::isnan(j.threshold)) return fail(AMAP_E_INVAL, "threshold must not be NaN");
+    return AMAP_OK;
+}
+
+// Workspace of one job: [signal spectrum | signal kappa | starlet scratch | noise].
+static size_t job_workspace_bytes(amap_dtype dt, const amap_job& j) {
+    const size_t plane = (size_t)j.n * j.n * esize(dt);
+    size_t b = align256(2 * plane) + align256(plane) + align256(plane);
+    if (j.n_real >= 2) b += noise_workspace_bytes(dt, j.n, j.J, j.n_real);
+    return b;
+}
+
+}  // extern "C"
+
+template <typename T>
+static amap_status enqueue_job(const amap_ctx* c, char* w, const amap_job& j, hipStream_t s) {
+    const size_t plane = (size_t)j.n * j.n * sizeof(T);
+    const int logn = ilog2(j.n);
+    const long long n2 = (long long)j.n * j.n;
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(w);
+    T* kap = j.kappa_e ? (T*)j.kappa_e : reinterpret_cast<T*>(w + align256(2 * plane));
+    T* tmp = reinterpret_cast<T*>(w + align256(2 * plane) + align256(plane));
+    char* nws = w + align256(2 * plane) + 2 * align256(plane);
+    AMAP_TRY(enqueue_ks<T>(c, logn, 1, (const T*)j.g1, (const T*)j.g2, 0, C, kap, nullptr, n2,
+                           false, 0, 0, s));
+    AMAP_TRY(enqueue_starlet<T>(logn, j.J, 1, kap, n2, (T*)j.planes, (long long)j.J * n2, tmp, s));
+    if (j.n_real < 2) return AMAP_OK;
+    AMAP_TRY(enqueue_noise<T>(c, nws, j.n, j.J, (const T*)j.g1, (const T*)j.g2, j.n_real, j.seed,
+                              (const T*)j.planes, (T*)j.sigma, (T*)j.snr, s));
+    AMAP_HIP(launch_count_peaks<T>(logn, j.J - 1, (const T*)j.snr, j.threshold, j.peaks, s),
+             "peak kernel");
+    return AMAP_OK;
+}
+
+extern "C" {
+
+amap_status amap_run_path(amap_ctx_t c, amap_dtype dt, int n, int J, const void* g1,
+                          const void* g2, int n_real, uint64_t seed, double threshold,
+                          void* kappa_e, void* kappa_b, void* planes, void* sigma, void* snr,
+                          long long* peaks, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    amap_job j;
+    j.n = n; j.J = J; j.n_real = n_real; j.seed = seed; j.threshold = threshold;
+    j.g1 = g1; j.g2 = g2; j.kappa_e = kappa_e; j.planes = planes; j.sigma = sigma;
+    j.snr = snr; j.peaks = peaks;
+    if (n_real < 2) return fail(AMAP_E_INVAL, "n_real must be >= 2 (got %d)", n_real);
+    AMAP_TRY(validate_job(dt, j));
+    AMAP_TRY(check_ptr(kappa_b, "kappa_b", false));
+    const size_t plane = (size_t)n * n * esize(dt);
+    if (overlaps(kappa_b, plane, planes, plane * J) || overlaps(kappa_b, plane, g1, plane) ||
+        overlaps(kappa_b, plane, g2, plane) || overlaps(kappa_b, plane, kappa_e, plane))
+        return fail(AMAP_E_INVAL, "kappa_b may not overlap inputs or other outputs");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_TRY(c->ws.reserve(job_workspace_bytes(dt, j)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(c->ws.ptr);
+    if (kappa_b) {
+        // kappa_B is an extra output of the signal's KS pass only
+        AMAP_TRY(dt == AMAP_F32
+                 ? enqueue_ks<float>(c, ilog2(n), 1, (const float*)g1, (const float*)g2, 0,
+                                     (cpx<float>*)w, (float*)(w + align256(2 * plane)),
+                                     (float*)kappa_b, (long long)n * n, false, 0, 0, s)
+                 : enqueue_ks<double>(c, ilog2(n), 1, (const double*)g1, (const double*)g2, 0,
+                                      (cpx<double>*)w, (double*)(w + align256(2 * plane)),
+                                      (double*)kappa_b, (long long)n * n, false, 0, 0, s));
+    }
+    return dt == AMAP_F32 ? enqueue_job<float>(c, w, j, s) : enqueue_job<double>(c, w, j, s);
+}
+
+size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real) {
+    if (check_dtype(dt) != AMAP_OK || check_n(n) != AMAP_OK || check_J(n, J) != AMAP_OK) return 0;
+    amap_job j;
+    std::memset(&j, 0, sizeof j);
+    j.n = n; j.J = J; j.n_real = n_real >= 2 ? n_real : 0;
+    return job_workspace_bytes(dt, j);
+}
+
+}  // extern "C"
+
+struct amap_plan {
+    amap_ctx* ctx = nullptr;
+    amap_dtype dt = AMAP_F32;
+    std::vector<amap_job> jobs;
+    Workspace ws;
+    hipStream_t graph_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_stream = nullptr;
+    }
+};
+
+static amap_status enqueue_plan(amap_plan* p, hipStream_t s) {
+    char* w = static_cast<char*>(p->ws.ptr);
+    for (const amap_job& j : p->jobs)
+        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_job<float>(p->ctx, w, j, s)
+                                   : enqueue_job<double>(p->ctx, w, j, s));
+    return AMAP_OK;
+}
+
+extern "C" {
+
+amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, int njobs,
+                            amap_plan_t* out) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!out) return fail(AMAP_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    if (njobs < 1 || !jobs) return fail(AMAP_E_INVAL, "need at least one job");
+    size_t need = 0;
+    for (int i = 0; i < njobs; ++i) {
+        amap_status st = validate_job(dt, jobs[i]);
+        if (st != AMAP_OK) {
+            std::string m = g_last_error;
+            return fail(st, "job %d: %s", i, m.c_str());
+        }
+        if (jobs[i].n_real == 1 || jobs[i].n_real < 0)
+            return fail(AMAP_E_INVAL, "job %d: n_real must be 0 or >= 2", i);
+        const size_t b = job_workspace_bytes(dt, jobs[i]);
+        need = b > need ? b : need;
+    }
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    amap_plan* p = new (std::nothrow) amap_plan;
+    if (!p) return fail(AMAP_E_NOMEM, "out of host memory");
+    p->ctx = c;
+    p->dt = dt;
+    p->jobs.assign(jobs, jobs + njobs);
+    amap_status st = p->ws.reserve(need);
+    if (st != AMAP_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return AMAP_OK;
+}
+
+amap_status amap_batch_run(amap_plan_t p, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(AMAP_E_INVAL, "plan must not be NULL");
+    DeviceGuard g(p->ctx->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", p->ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!s) return enqueue_plan(p, s);  // the null stream cannot be captured
+    if (!p->exec || p->graph_stream != s) {
+        p->drop_graph();
+        AMAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+        amap_status st = enqueue_plan(p, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != AMAP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        p->graph = graph;
+        e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            p->drop_graph();
+            return hip_fail(e, "graph instantiate");
+        }
+        p->graph_stream = s;
+    }
+    AMAP_HIP(hipGraphLaunch(p->exec, s), "graph launch");
+    return AMAP_OK;
+}
+
+amap_status amap_plan_destroy(amap_plan_t p) {
+    g_last_error.clear();
+    if (!p) return AMAP_OK;
+    DeviceGuard g(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    p->drop_graph();
+    p->ws.release();
+    delete p;
+    return AMAP_OK;
+}
+
+}  // extern "C"
