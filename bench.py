@@ -37,33 +37,32 @@ GRF_SEED, NOISE_SEED = 11, 12
 def kernel_model(name, n, J, batch_real):
     """Algorithmic bytes and flops of one launch of each kernel (float32).
 
-    bytes: the kernel's compulsory input + output (each operand read or
-    written once); flops: 5 m log2 m per length-m complex FFT, 6 per complex
-    multiply, 9 per 5-tap B3 filter output, 1 per difference.
+    bytes: the kernel's compulsory input + output, each operand read or
+    written once per launch (the shared shear map once per launch; the
+    double-precision noise accumulators read and written once per launch);
+    flops: 5 m log2 m per length-m complex FFT, 6 per complex multiply,
+    19 per pixel and starlet scale (two 5-tap B3 filters and a difference),
+    4 per pixel and scale for the running mean and squared deviation.
     """
-    n2 = n * n
+    n2 = float(n * n)
     lg = n.bit_length() - 1
     B = batch_real
     fft1d = 5.0 * n2 * lg  # n transforms of length n
-    if name == "ks_cols_fwd_rotate":  # shared shear read once, B spectra written
-        return 8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 6.0 * n2)
-    if name == "ks_cols_fwd":
-        return 16.0 * n2 * B, B * fft1d
-    if name == "ks_rows":
-        return 16.0 * n2 * B, B * (2 * fft1d + 6.0 * n2)
-    if name == "ks_cols_inv":
-        return 12.0 * n2 * B, B * fft1d
-    if name == "starlet_row":
-        return 8.0 * n2 * B, 9.0 * n2 * B
-    if name == "starlet_col":
-        return 16.0 * n2 * B, 10.0 * n2 * B
-    if name == "noise_accumulate":
-        return (4.0 * (J - 1) * B + 32.0 * (J - 1)) * n2, 3.0 * (J - 1) * n2 * B
-    if name == "noise_finalize":
-        return (16.0 + 12.0) * (J - 1) * n2, 4.0 * (J - 1) * n2
-    if name == "count_peaks":
-        return 4.0 * (J - 1) * n2, 9.0 * (J - 1) * n2
-    return None, None
+    scales_last = (J - 1) - 3 * ((J - 2) // 3)  # scales in the last stage
+    models = {
+        "ks_cols_fwd_rotate": (8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 6.0 * n2)),
+        "ks_cols_fwd": (16.0 * n2, fft1d),
+        "ks_rows": (16.0 * n2 * B, B * (2 * fft1d + 6.0 * n2)),
+        "ks_cols_inv": (12.0 * n2 * B, B * fft1d),
+        "noise_stage_j1": ((8.0 * B + 96.0) * n2, 3 * (19.0 + 4.0) * n2 * B),
+        "noise_stage_j4": ((4.0 * B + 32.0 * scales_last) * n2,
+                           scales_last * (19.0 + 4.0) * n2 * B),
+        "starlet_stage_j1": (20.0 * n2, 3 * 19.0 * n2),
+        "starlet_stage_j4": ((8.0 + 4.0 * scales_last) * n2, scales_last * 19.0 * n2),
+        "noise_finalize": ((16.0 + 12.0) * (J - 1) * n2, 3.0 * (J - 1) * n2),
+        "count_peaks": (4.0 * (J - 1) * n2, 9.0 * (J - 1) * n2),
+    }
+    return models.get(name, (None, None))
 
 
 def cpu_baseline(g1, g2, budget_s):
@@ -165,12 +164,18 @@ def main():
     dom = max(ktimes.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = ktimes[dom][1] / ktimes[dom][0] * 1e-3
     b_alg, f_alg = kernel_model(dom, N, J, B)
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": b_alg / dom_avg_s / 1e9,
+    for name, rec in kernels.items():
+        bb, ff = kernel_model(name, N, J, B)
+        if bb is not None:
+            rec["alg_GBps"] = bb / (rec["avg_us"] * 1e-6) / 1e9
+            rec["alg_TFLOPs"] = ff / (rec["avg_us"] * 1e-6) / 1e12
+    roofline = {"kernel": dom, "bound": "hbm",
+                "achieved": b_alg / dom_avg_s / 1e9 if b_alg else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
                 "bytes_per_launch": b_alg, "avg_launch_us": dom_avg_s * 1e6,
                 "flops_per_launch": f_alg,
                 "tflops": f_alg / dom_avg_s / 1e12 if f_alg else None}
-    roofline["frac"] = roofline["achieved"] / roofline["peak"]
+    roofline["frac"] = roofline["achieved"] / roofline["peak"] if b_alg else None
 
     # plain path: one map, KS + starlet, one launch sequence per map
     ke = out["kappa_e"]

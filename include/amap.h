@@ -144,9 +144,12 @@ amap_status amap_map_direct(amap_ctx_t ctx, amap_dtype dt, int n,
  * r = 0 .. n_real-1 every pixel's shear is rotated by beta = 2 pi u,
  * gamma' = gamma exp(i beta), with u the Philox4x64-10 uniform of
  * amap_phase_uniforms; gamma' goes through the same KS inversion and
- * starlet transform as the signal.  Per pixel and scale:
- *   sigma_j = sqrt( (sum_r w^2 - (sum_r w)^2 / R) / (R - 1) ),
- * accumulated in double precision.  If snr is not NULL, planes_signal
+ * starlet transform as the signal.  Per pixel and scale, the unbiased
+ * sample standard deviation over the realisations,
+ *   sigma_j = sqrt( sum_r (w_r - mean_r w)^2 / (R - 1) ),
+ * kept as a running mean and sum of squared deviations (Welford's update
+ * within a batch of realisations, merged across batches in double
+ * precision).  If snr is not NULL, planes_signal
  * (J*n*n, the signal's planes) must be given and snr_j = w_j / sigma_j
  * (0 where sigma_j = 0).  sigma, snr: (J-1)*n*n.  n_real >= 2.
  */

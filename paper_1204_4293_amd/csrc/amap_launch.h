@@ -51,16 +51,26 @@ struct KsArgs {
 };
 template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 
-// Starlet decomposition of `batch` maps: kappa at + b*in_stride, planes at
-// + b*planes_stride (J planes of n*n), tmp: batch*n*n scratch.
+// Starlet decomposition of `batch` maps (kappa at + b*in_stride).
+//   WRITE (S1 == null): planes at + b*planes_stride (J planes of n*n)
+//   ACC   (M != null):  noise realisations; M/M2 [J-1][n*n] double running
+//                       mean and sum of squared deviations of w_j over the
+//                       `done` realisations merged so far; planes unused
+// Scratch (each batch*n*n): cbuf0 (always), cbuf1 (ACC), tmp; wbuf (ACC):
+// 3*batch*n*n, the detail planes of one stage.
 template <typename T>
 struct StarletArgs {
-    int logn, J, batch;
+    int logn, J, batch, done;
     const T* kappa;
     long long in_stride;
     T* planes;
     long long planes_stride;
+    T* cbuf0;
+    T* cbuf1;
     T* tmp;
+    T* wbuf;
+    double* M;
+    double* M2;
     hipStream_t stream;
 };
 template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
@@ -68,15 +78,9 @@ template <typename T>
 hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStream_t s);
 
 // Noise statistics.
-//   accumulate: S1[j] += sum_b w_{b,j}, S2[j] += sum_b w_{b,j}^2 over `batch`
-//   realisations whose planes sit at planes + b*planes_stride (j < J-1)
+// sigma = sqrt(M2/(R-1)); snr = w/sigma (0 where sigma = 0) if snr
 template <typename T>
-hipError_t launch_noise_accumulate(int logn, int J, int batch, const T* planes,
-                                   long long planes_stride, double* S1, double* S2,
-                                   hipStream_t s);
-// sigma = sqrt((S2 - S1^2/R)/(R-1)); snr = w/sigma (0 where sigma = 0) if snr
-template <typename T>
-hipError_t launch_noise_finalize(int logn, int J, int R, const double* S1, const double* S2,
+hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s);
 hipError_t launch_zero_f64(double* p, long long count, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long count, hipStream_t s);

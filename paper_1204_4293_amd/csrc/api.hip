@@ -275,12 +275,17 @@ amap_status enqueue_ks(const amap_ctx* ctx, int logn, int batch, const T* g1, co
     return AMAP_OK;
 }
 
+// Signal-path starlet: `scratch` holds 2*batch*n*n elements (c ping-pong
+// buffer and the per-scale row-pass scratch).
 template <typename T>
 amap_status enqueue_starlet(int logn, int J, int batch, const T* kappa, long long in_stride,
-                            T* planes, long long planes_stride, T* tmp, hipStream_t s) {
+                            T* planes, long long planes_stride, T* scratch, hipStream_t s) {
+    const long long n2 = 1ll << (2 * logn);
     StarletArgs<T> a;
-    a.logn = logn; a.J = J; a.batch = batch; a.kappa = kappa; a.in_stride = in_stride;
-    a.planes = planes; a.planes_stride = planes_stride; a.tmp = tmp; a.stream = s;
+    a.logn = logn; a.J = J; a.batch = batch; a.done = 0; a.kappa = kappa; a.in_stride = in_stride;
+    a.planes = planes; a.planes_stride = planes_stride;
+    a.cbuf0 = scratch; a.cbuf1 = nullptr; a.tmp = scratch + (long long)batch * n2; a.wbuf = nullptr;
+    a.M = nullptr; a.M2 = nullptr; a.stream = s;
     AMAP_HIP(launch_starlet<T>(a), "starlet kernels");
     return AMAP_OK;
 }
@@ -298,10 +303,9 @@ size_t noise_workspace_bytes(amap_dtype dt, int n, int J, int n_real) {
     const size_t n2 = (size_t)n * n, e = esize(dt);
     const size_t B = (size_t)noise_batch(n, n_real);
     return align256(B * n2 * 2 * e)            // complex spectra
-         + align256(B * n2 * e)                // kappa of each realisation
-         + align256(B * n2 * (size_t)J * e)    // planes of each realisation
-         + align256(B * n2 * e)                // starlet row-pass scratch
-         + 2 * align256((size_t)(J - 1) * n2 * 8);  // S1, S2
+         + 4 * align256(B * n2 * e)            // kappa, two c buffers, row scratch
+         + align256(3 * B * n2 * e)            // detail planes of one stage
+         + 2 * align256((size_t)(J - 1) * n2 * 8);  // running mean, M2
 }
 
 template <typename T>
@@ -311,24 +315,29 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
     const int logn = ilog2(n);
     const long long n2 = (long long)n * n;
     const int B = noise_batch(n, n_real);
+    const size_t plane_b = align256((size_t)B * n2 * sizeof(T));
     char* p = ws;
     cpx<T>* C = reinterpret_cast<cpx<T>*>(p);   p += align256((size_t)B * n2 * 2 * sizeof(T));
-    T* kap = reinterpret_cast<T*>(p);            p += align256((size_t)B * n2 * sizeof(T));
-    T* planes = reinterpret_cast<T*>(p);         p += align256((size_t)B * n2 * J * sizeof(T));
-    T* tmp = reinterpret_cast<T*>(p);            p += align256((size_t)B * n2 * sizeof(T));
-    double* S1 = reinterpret_cast<double*>(p);   p += align256((size_t)(J - 1) * n2 * 8);
-    double* S2 = reinterpret_cast<double*>(p);
-    AMAP_HIP(launch_zero_f64(S1, (long long)(J - 1) * n2, s), "zero accumulators");
-    AMAP_HIP(launch_zero_f64(S2, (long long)(J - 1) * n2, s), "zero accumulators");
+    T* kap = reinterpret_cast<T*>(p);            p += plane_b;
+    T* cb0 = reinterpret_cast<T*>(p);            p += plane_b;
+    T* cb1 = reinterpret_cast<T*>(p);            p += plane_b;
+    T* tmp = reinterpret_cast<T*>(p);            p += plane_b;
+    T* wb = reinterpret_cast<T*>(p);             p += align256((size_t)3 * B * n2 * sizeof(T));
+    double* M = reinterpret_cast<double*>(p);    p += align256((size_t)(J - 1) * n2 * 8);
+    double* M2 = reinterpret_cast<double*>(p);
+    AMAP_HIP(launch_zero_f64(M, (long long)(J - 1) * n2, s), "zero accumulators");
+    AMAP_HIP(launch_zero_f64(M2, (long long)(J - 1) * n2, s), "zero accumulators");
     for (int r0 = 0; r0 < n_real; r0 += B) {
         const int bb = (n_real - r0) < B ? (n_real - r0) : B;
         AMAP_TRY(enqueue_ks<T>(ctx, logn, bb, g1, g2, 0, C, kap, nullptr, n2, true, seed,
                                (uint64_t)r0, s));
-        AMAP_TRY(enqueue_starlet<T>(logn, J, bb, kap, n2, planes, (long long)J * n2, tmp, s));
-        AMAP_HIP(launch_noise_accumulate<T>(logn, J, bb, planes, (long long)J * n2, S1, S2, s),
-                 "noise accumulation");
+        StarletArgs<T> a;
+        a.logn = logn; a.J = J; a.batch = bb; a.done = r0; a.kappa = kap; a.in_stride = n2;
+        a.planes = nullptr; a.planes_stride = 0; a.cbuf0 = cb0; a.cbuf1 = cb1; a.tmp = tmp;
+        a.wbuf = wb; a.M = M; a.M2 = M2; a.stream = s;
+        AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
-    AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, S1, S2, planes_signal, sigma, snr, s),
+    AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s),
              "noise finalize");
     return AMAP_OK;
 }
@@ -476,7 +485,7 @@ amap_status amap_starlet_forward(amap_ctx_t c, amap_dtype dt, int n, int J, cons
     DeviceGuard g(c->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
     TimerScope ts(c);
-    AMAP_TRY(c->ws.reserve(plane));
+    AMAP_TRY(c->ws.reserve(2 * plane));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int logn = ilog2(n);
     const long long n2 = (long long)n * n;
@@ -675,7 +684,7 @@ static amap_status validate_job(amap_dtype dt, const amap_job& j) {
 // Workspace of one job: [signal spectrum | signal kappa | starlet scratch | noise].
 static size_t job_workspace_bytes(amap_dtype dt, const amap_job& j) {
     const size_t plane = (size_t)j.n * j.n * esize(dt);
-    size_t b = align256(2 * plane) + align256(plane) + align256(plane);
+    size_t b = align256(2 * plane) + align256(plane) + align256(2 * plane);
     if (j.n_real >= 2) b += noise_workspace_bytes(dt, j.n, j.J, j.n_real);
     return b;
 }
@@ -690,7 +699,7 @@ static amap_status enqueue_job(const amap_ctx* c, char* w, const amap_job& j, hi
     cpx<T>* C = reinterpret_cast<cpx<T>*>(w);
     T* kap = j.kappa_e ? (T*)j.kappa_e : reinterpret_cast<T*>(w + align256(2 * plane));
     T* tmp = reinterpret_cast<T*>(w + align256(2 * plane) + align256(plane));
-    char* nws = w + align256(2 * plane) + 2 * align256(plane);
+    char* nws = w + align256(2 * plane) + align256(plane) + align256(2 * plane);
     AMAP_TRY(enqueue_ks<T>(c, logn, 1, (const T*)j.g1, (const T*)j.g2, 0, C, kap, nullptr, n2,
                            false, 0, 0, s));
     AMAP_TRY(enqueue_starlet<T>(logn, j.J, 1, kap, n2, (T*)j.planes, (long long)j.J * n2, tmp, s));

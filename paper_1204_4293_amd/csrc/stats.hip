@@ -6,36 +6,15 @@
 
 namespace amap {
 
-// S1[j] += sum_b w_{b,j};  S2[j] += sum_b w_{b,j}^2   (double accumulators)
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_noise_accumulate(const T* __restrict__ planes, long long planes_stride, int batch, int J,
-                   long long n2, double* __restrict__ S1, double* __restrict__ S2) {
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n2) return;
-    for (int j = 0; j < J - 1; ++j) {
-        double s1 = 0.0, s2 = 0.0;
-        for (int b = 0; b < batch; ++b) {
-            const double w = (double)planes[(long long)b * planes_stride + (long long)j * n2 + idx];
-            s1 += w;
-            s2 += w * w;
-        }
-        S1[(long long)j * n2 + idx] += s1;
-        S2[(long long)j * n2 + idx] += s2;
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_noise_finalize(const double* __restrict__ S1, const double* __restrict__ S2, int R, int J,
-                 long long n2, const T* __restrict__ planes_signal, T* __restrict__ sigma,
-                 T* __restrict__ snr) {
+k_noise_finalize(const double* __restrict__ M2, int R, int J, long long n2,
+                 const T* __restrict__ planes_signal, T* __restrict__ sigma, T* __restrict__ snr) {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= n2) return;
     for (int j = 0; j < J - 1; ++j) {
         const long long e = (long long)j * n2 + idx;
-        const double s1 = S1[e];
-        double var = (S2[e] - s1 * s1 / (double)R) / (double)(R - 1);
+        double var = M2[e] / (double)(R - 1);
         var = var > 0.0 ? var : 0.0;
         const T sg = (T)sqrt(var);
         sigma[e] = sg;
@@ -98,23 +77,12 @@ k_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* __restrict__ out) {
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
 
 template <typename T>
-hipError_t launch_noise_accumulate(int logn, int J, int batch, const T* planes,
-                                   long long planes_stride, double* S1, double* S2,
-                                   hipStream_t s) {
-    const long long n2 = 1ll << (2 * logn);
-    AMAP_LAUNCH("noise_accumulate", s,
-                k_noise_accumulate<T><<<blocks_for(n2), 256, 0, s>>>(planes, planes_stride, batch,
-                                                                     J, n2, S1, S2));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_noise_finalize(int logn, int J, int R, const double* S1, const double* S2,
+hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s) {
     const long long n2 = 1ll << (2 * logn);
     AMAP_LAUNCH("noise_finalize", s,
-                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(S1, S2, R, J, n2,
-                                                                   planes_signal, sigma, snr));
+                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(M2, R, J, n2, planes_signal,
+                                                                   sigma, snr));
     return hipGetLastError();
 }
 
@@ -145,14 +113,10 @@ hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, 
     return hipGetLastError();
 }
 
-template hipError_t launch_noise_accumulate<float>(int, int, int, const float*, long long, double*,
-                                                   double*, hipStream_t);
-template hipError_t launch_noise_accumulate<double>(int, int, int, const double*, long long, double*,
-                                                    double*, hipStream_t);
-template hipError_t launch_noise_finalize<float>(int, int, int, const double*, const double*,
-                                                 const float*, float*, float*, hipStream_t);
+template hipError_t launch_noise_finalize<float>(int, int, int, const double*, const float*, float*,
+                                                 float*, hipStream_t);
 template hipError_t launch_noise_finalize<double>(int, int, int, const double*, const double*,
-                                                  const double*, double*, double*, hipStream_t);
+                                                  double*, double*, hipStream_t);
 template hipError_t launch_count_peaks<float>(int, int, const float*, double, long long*, hipStream_t);
 template hipError_t launch_count_peaks<double>(int, int, const double*, double, long long*, hipStream_t);
 

@@ -81,8 +81,8 @@ def test_ks_recovers_emode_kappa_on_gpu(ctx):
 
 # ---- starlet ------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,J", [(16, 2), (16, 4), (64, 6), (128, 7), (256, 5), (256, 8),
-                                 (1024, 7), (2048, 9), (4096, 9)])
+@pytest.mark.parametrize("n,J", [(16, 2), (16, 4), (32, 5), (64, 6), (128, 7), (256, 5), (256, 8),
+                                 (1024, 7), (1024, 10), (2048, 9), (4096, 9), (4096, 12)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_starlet_forward(ctx, n, J, dtype):
     if dtype == torch.float64 and n > 1024:
@@ -126,7 +126,8 @@ def test_phase_uniforms_bit_exact(ctx, n, seed, r):
 
 @pytest.mark.parametrize("n,J,R,dtype", [(64, 4, 8, torch.float32), (128, 5, 20, torch.float32),
                                          (256, 5, 5, torch.float32), (64, 3, 3, torch.float64),
-                                         (1024, 7, 18, torch.float32)])
+                                         (256, 8, 4, torch.float32), (256, 5, 3, torch.float64),
+                                         (1024, 7, 18, torch.float32), (1024, 10, 3, torch.float32)])
 def test_noise_maps_and_snr(ctx, n, J, R, dtype):
     print("noise n=%d J=%d R=%d %s" % (n, J, R, dtype), flush=True)
     seed = 40 + n
@@ -140,8 +141,17 @@ def test_noise_maps_and_snr(ctx, n, J, R, dtype):
     sigma, snr = ctx.noise_maps(t1, t2, J, R, seed, planes_signal=planes)
     torch.cuda.synchronize()
     r = rms(kE)
-    assert maxerr(host(sigma), sig_ref) <= TOL[dtype] * r
-    assert np.all(np.abs(host(snr) - snr_ref) * sig_ref <= TOL[dtype] * r)
+    tol = TOL[dtype] * r
+    sg, sn = host(sigma), host(snr)
+    assert maxerr(sg, sig_ref) <= tol
+    # S = w / sigma: errors of w and sigma (each within tol) propagate as
+    # sigma |dS| <= |dw| + |S| |dsigma| <= tol (1 + |S|)
+    assert np.all(np.abs(sn - snr_ref) * sig_ref <= tol * (1.0 + np.abs(snr_ref)) * (1 + 1e-6))
+    # and the stored quotient reproduces the signal plane wherever sigma > 0
+    w = planes_ref[: J - 1]
+    nz = sg > 0
+    assert np.max(np.abs(sn * sg - w)[nz]) <= 2 * tol
+    assert np.all(sn[~nz] == 0.0)
 
 
 def test_noise_expected_variance_full_size(ctx):
