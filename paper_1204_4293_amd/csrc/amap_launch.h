@@ -71,8 +71,11 @@ struct StarletArgs {
     T* wbuf;
     double* M;
     double* M2;
+    void* part;         // ACC: per-group partial statistics (starlet_partials_bytes)
     hipStream_t stream;
 };
+// Bytes of per-group partial statistics a noise batch may need.
+size_t starlet_partials_bytes(int logn, int batch);
 template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
 template <typename T>
 hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStream_t s);

@@ -285,7 +285,7 @@ amap_status enqueue_starlet(int logn, int J, int batch, const T* kappa, long lon
     a.logn = logn; a.J = J; a.batch = batch; a.done = 0; a.kappa = kappa; a.in_stride = in_stride;
     a.planes = planes; a.planes_stride = planes_stride;
     a.cbuf0 = scratch; a.cbuf1 = nullptr; a.tmp = scratch + (long long)batch * n2; a.wbuf = nullptr;
-    a.M = nullptr; a.M2 = nullptr; a.stream = s;
+    a.M = nullptr; a.M2 = nullptr; a.part = nullptr; a.stream = s;
     AMAP_HIP(launch_starlet<T>(a), "starlet kernels");
     return AMAP_OK;
 }
@@ -305,6 +305,7 @@ size_t noise_workspace_bytes(amap_dtype dt, int n, int J, int n_real) {
     return align256(B * n2 * 2 * e)            // complex spectra
          + 4 * align256(B * n2 * e)            // kappa, two c buffers, row scratch
          + align256(3 * B * n2 * e)            // detail planes of one stage
+         + align256(starlet_partials_bytes(ilog2(n), (int)B))  // per-group partials
          + 2 * align256((size_t)(J - 1) * n2 * 8);  // running mean, M2
 }
 
@@ -323,6 +324,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
     T* cb1 = reinterpret_cast<T*>(p);            p += plane_b;
     T* tmp = reinterpret_cast<T*>(p);            p += plane_b;
     T* wb = reinterpret_cast<T*>(p);             p += align256((size_t)3 * B * n2 * sizeof(T));
+    void* part = p;                              p += align256(starlet_partials_bytes(logn, B));
     double* M = reinterpret_cast<double*>(p);    p += align256((size_t)(J - 1) * n2 * 8);
     double* M2 = reinterpret_cast<double*>(p);
     AMAP_HIP(launch_zero_f64(M, (long long)(J - 1) * n2, s), "zero accumulators");
@@ -334,7 +336,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
         StarletArgs<T> a;
         a.logn = logn; a.J = J; a.batch = bb; a.done = r0; a.kappa = kap; a.in_stride = n2;
         a.planes = nullptr; a.planes_stride = 0; a.cbuf0 = cb0; a.cbuf1 = cb1; a.tmp = tmp;
-        a.wbuf = wb; a.M = M; a.M2 = M2; a.stream = s;
+        a.wbuf = wb; a.M = M; a.M2 = M2; a.part = part; a.stream = s;
         AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
     AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s),

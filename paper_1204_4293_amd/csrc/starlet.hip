@@ -36,7 +36,6 @@ __device__ __forceinline__ T b3_combine(T a0, T a1, T a2, T a3, T a4) {
     return ((a0 + a4) + (T)4 * (a1 + a3) + (T)6 * a2) * (T)0.0625;
 }
 
-constexpr int kPx = 8;           // output pixels owned per thread
 constexpr int kLdsBytes = 160 * 1024 - 1024;
 
 template <typename T>
@@ -52,93 +51,408 @@ struct StageArgs {
     long long cout_stride;
 };
 
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
-    extern __shared__ unsigned char smem_raw[];
-    constexpr int NW = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = 1 << a.logn, m = n - 1;
-    const long long n2 = (long long)n * n;
-    const int tw = 1 << a.log_tw, twm = tw - 1;
-    const int d0 = 1 << (a.j0 - 1);
-    const int Hx = 2 * d0 * ((1 << a.ns) - 1);
-    const int Hv = 2 * ((1 << a.ns) - 1);
-    const int TXT = tw + 2 * Hx, TVT = a.th + 2 * Hv;
-    T* A = reinterpret_cast<T*>(smem_raw);
-    T* Bf = A + TXT * TVT;
+// 16-byte vectors: four floats or two doubles
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; static constexpr int G = 4; };
+template <> struct Vec<double> { using type = double2; static constexpr int G = 2; };
+
+template <typename T, int G>
+struct VArr { T e[G]; };
+
+template <typename T, int G>
+__device__ __forceinline__ VArr<T, G> vload(const T* p) {
+    const typename Vec<T>::type v = *reinterpret_cast<const typename Vec<T>::type*>(p);
+    VArr<T, G> r;
+    if constexpr (G == 4) { r.e[0] = v.x; r.e[1] = v.y; r.e[2] = v.z; r.e[3] = v.w; }
+    else { r.e[0] = v.x; r.e[1] = v.y; }
+    return r;
+}
+template <typename T, int G>
+__device__ __forceinline__ void vstore(T* p, const VArr<T, G>& r) {
+    typename Vec<T>::type v;
+    if constexpr (G == 4) { v.x = r.e[0]; v.y = r.e[1]; v.z = r.e[2]; v.w = r.e[3]; }
+    else { v.x = r.e[0]; v.y = r.e[1]; }
+    *reinterpret_cast<typename Vec<T>::type*>(p) = v;
+}
+template <typename T, int G>
+__device__ __forceinline__ VArr<T, G> vcombine(const VArr<T, G>& a0, const VArr<T, G>& a1,
+                                               const VArr<T, G>& a2, const VArr<T, G>& a3,
+                                               const VArr<T, G>& a4) {
+    VArr<T, G> r;
+#pragma unroll
+    for (int c = 0; c < G; ++c) r.e[c] = b3_combine(a0.e[c], a1.e[c], a2.e[c], a3.e[c], a4.e[c]);
+    return r;
+}
+
+// Geometry shared by the host planner and the kernel: the x halo is rounded
+// up to whole vectors so the output tile starts on a vector boundary; each
+// LDS row has one vector of padding on either side (read only by outputs
+// outside the valid region).
+__host__ __device__ inline int stage_hx(int d0, int ns, int G) {
+    const int h = 2 * d0 * ((1 << ns) - 1);
+    return (h + G - 1) / G * G;
+}
+
+constexpr int kSegLen = 4;        // column-pass outputs per sliding window
+constexpr int kVecPerThread = 2;  // owned output vectors per thread
+constexpr int kPrefetch = 6;      // tile vectors per thread held while prefetching
+
+// Barrier that orders only LDS accesses, so global loads issued before it
+// (the next tile's prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Geometry of one tile of a stage, shared by the write and noise kernels.
+struct TileGeom {
+    int n, m, d0, Hx, Hv, TXT, TVT, RS, tw, log_tw, th, x0, v0, q, nvec;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(int logn, int j0, int ns, int log_tw, int th,
+                                              int G) {
+    TileGeom g;
+    g.n = 1 << logn; g.m = g.n - 1;
+    g.tw = 1 << log_tw; g.log_tw = log_tw; g.th = th;
+    g.d0 = 1 << (j0 - 1);
+    g.Hx = stage_hx(g.d0, ns, G);
+    g.Hv = 2 * ((1 << ns) - 1);
+    g.TXT = g.tw + 2 * g.Hx; g.TVT = th + 2 * g.Hv;
+    g.RS = g.TXT + 2 * G;
     // tile index: x-tiles fastest, then sub-row tiles, then the row residue;
     // consecutive tiles (which share halos) are kept on one XCD
-    const int ntx = n >> a.log_tw, ntv = (n / d0) / a.th;
-    const int ntiles = ntx * ntv * d0;
+    const int ntx = g.n >> log_tw, ntv = (g.n / g.d0) / th;
+    const int ntiles = ntx * ntv * g.d0;
     int t = blockIdx.x;
     if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
-    const int xt = t % ntx, vt = (t / ntx) % ntv, q = t / (ntx * ntv);
-    const int x0 = xt * tw, v0 = vt * a.th;
-    const int npix = tw * a.th;
-    const int map = blockIdx.y;
-    const T* src = a.src + (long long)map * a.src_stride;
+    const int xt = t % ntx, vt = (t / ntx) % ntv;
+    g.q = t / (ntx * ntv);
+    g.x0 = xt * g.tw; g.v0 = vt * th;
+    g.nvec = (g.tw * th) / G;
+    return g;
+}
 
-    // load the tile with its halo (periodic), one wavefront per row
-    for (int v = wave; v < TVT; v += NW) {
-        const long long row = (long long)((q + d0 * (v0 - Hv + v)) & m) * n;
-        for (int i = lane; i < TXT; i += 64) A[v * TXT + i] = src[row + ((x0 - Hx + i) & m)];
-    }
-    __syncthreads();
+// Global row of tile row v, and global pixel row of owned output row pv.
+__device__ __forceinline__ long long tile_row(const TileGeom& g, int v) {
+    return (long long)((g.q + g.d0 * (g.v0 - g.Hv + v)) & g.m) * g.n;
+}
+__device__ __forceinline__ long long out_row(const TileGeom& g, int pv) {
+    return (long long)((g.q + g.d0 * (g.v0 + pv)) & g.m) * g.n;
+}
 
-    // c_{j-1} of the owned output pixels, carried from scale to scale
-    T prev[kPx];
-#pragma unroll
-    for (int k = 0; k < kPx; ++k) {
-        const int p = tid + k * NT;
-        if (p < npix) prev[k] = A[(Hv + (p >> a.log_tw)) * TXT + Hx + (p & twm)];
-    }
-    int xlo = 0, xhi = TXT, vlo = 0, vhi = TVT;
-    for (int s = 0; s < a.ns; ++s) {
-        const int dx = d0 << s, dv = 1 << s;
-        // row pass A -> B over rows [vlo, vhi), pixels [rlo, rhi)
+// Splits e into (e / d, e % d) with a float reciprocal; exact for e < 16384
+// and d <= 1024 (checked exhaustively on the host).
+__device__ __forceinline__ int fdiv(int e, float inv_d) {
+    return (int)(((float)e + 0.5f) * inv_d);
+}
+
+// Runs the ns scales of a stage on the tile in A (B is scratch).  prev holds
+// c_{j0-1} of the owned vectors on entry and the stage's last c on exit;
+// wfn(s, k, pv, px, w) receives w_{j0+s} of owned vector k.  Work items are
+// (row, vector) pairs spread over all threads; each thread takes two row
+// items at a time so their LDS reads overlap.
+template <typename T, int NT, int KV, typename WFn>
+__device__ __forceinline__ void tile_scales(T* A, T* Bf, const TileGeom& g, int ns,
+                                            VArr<T, Vec<T>::G> (&prev)[KV], WFn wfn) {
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    const int tid = threadIdx.x;
+    const int RS = g.RS, twm = g.tw - 1;
+    int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
+    for (int s = 0; s < ns; ++s) {
+        const int dx = g.d0 << s, dv = 1 << s;
+        // row pass A -> B over rows [vlo, vhi), outputs [rlo, rhi) widened to
+        // whole vectors (the extra outputs stay outside the valid region)
         const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
-        for (int v = vlo + wave; v < vhi; v += NW) {
-            const T* ra = A + v * TXT;
-            T* rb = Bf + v * TXT;
-            for (int i = rlo + lane; i < rhi; i += 64)
-                rb[i] = b3_combine(ra[i - 2 * dx], ra[i - dx], ra[i], ra[i + dx], ra[i + 2 * dx]);
-        }
-        __syncthreads();
-        // column pass B -> A over rows [clo, chi), pixels [rlo, rhi)
-        const int clo = vlo + 2 * dv, chi = vhi - 2 * dv;
-        for (int v = clo + wave; v < chi; v += NW) {
-            const T* c0 = Bf + (v - 2 * dv) * TXT;
-            const int st = dv * TXT;
-            T* ra = A + v * TXT;
-            for (int i = rlo + lane; i < rhi; i += 64)
-                ra[i] = b3_combine(c0[i], c0[i + st], c0[i + 2 * st], c0[i + 3 * st], c0[i + 4 * st]);
-        }
-        __syncthreads();
-        // w_j of the owned pixels (the next row pass only reads A)
-        T* wplane = a.planes + (long long)map * a.planes_stride +
-                    (long long)(a.j0 + s - 1 - a.plane_base) * n2;
+        const int rlo4 = rlo / G * G;
+        const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
+        const float inv_nv = 1.0f / (float)nv;
+        const int rtot = nv * (vhi - vlo);
+        for (int e0 = tid; e0 < rtot; e0 += 2 * NT) {
+            VA o[2];
+            int off[2];
 #pragma unroll
-        for (int k = 0; k < kPx; ++k) {
+            for (int u = 0; u < 2; ++u) {
+                const int e = e0 + u * NT;
+                off[u] = -1;
+                if (e < rtot) {
+                    const int r = fdiv(e, inv_nv);
+                    const int i0 = rlo4 + (e - r * nv) * G;
+                    const T* ra = A + (vlo + r) * RS;
+                    off[u] = (vlo + r) * RS + i0;
+                    if (2 * dx <= G) {  // the five taps of all G outputs lie in three vectors
+                        const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
+                                 rr = vload<T, G>(ra + i0 + G);
+                        T w[3 * G];
+#pragma unroll
+                        for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
+#pragma unroll
+                        for (int k = 0; k < G; ++k) {
+                            const int b = G + k;
+                            o[u].e[k] = dx == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
+                                                : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
+                                                             w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
+                        }
+                    } else {  // dilation is a multiple of the vector width
+                        o[u] = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
+                                              vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
+                                              vload<T, G>(ra + i0 + 2 * dx));
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (off[u] >= 0) vstore<T, G>(Bf + off[u], o[u]);
+        }
+        lds_barrier();
+        // column pass B -> A: windows of kSegLen outputs along each chain
+        // v = clo + phase + dv*t, one vector column per item; all window
+        // values are read before any output is written
+        const int clo = vlo + 2 * dv, chi = vhi - 2 * dv;
+        const int lmax = (chi - clo + dv - 1) / dv;
+        const int nseg = (lmax + kSegLen - 1) / kSegLen;
+        const int items = nv * dv * nseg;
+        for (int it = tid; it < items; it += NT) {
+            const int r = fdiv(it, inv_nv);
+            const int i0 = rlo4 + (it - r * nv) * G;
+            const int phase = r & (dv - 1), seg = r >> s;
+            const int vfirst = clo + phase + dv * (seg * kSegLen);
+            if (vfirst >= chi) continue;
+            const T* col = Bf + i0;
+            VA win[kSegLen + 4];
+#pragma unroll
+            for (int k = 0; k < kSegLen + 4; ++k) {
+                const int v = vfirst + dv * (k - 2);
+                if (k < 4 || v < chi + 2 * dv) win[k] = vload<T, G>(col + v * RS);
+            }
+#pragma unroll
+            for (int k = 0; k < kSegLen; ++k) {
+                const int v = vfirst + dv * k;
+                if (v < chi)
+                    vstore<T, G>(A + v * RS + i0,
+                                 vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+            }
+        }
+        lds_barrier();
+        // w of the owned vectors (the next row pass only reads A)
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
             const int p = tid + k * NT;
-            if (p < npix) {
-                const int pv = p >> a.log_tw, px = p & twm;
-                const T c = A[(Hv + pv) * TXT + Hx + px];
-                wplane[(long long)((q + d0 * (v0 + pv)) & m) * n + x0 + px] = prev[k] - c;
+            if (p < g.nvec) {
+                const int e = p * G;
+                const int pv = e >> g.log_tw, px = e & twm;
+                const VA c = vload<T, G>(A + (g.Hv + pv) * RS + g.Hx + px);
+                VA wv;
+#pragma unroll
+                for (int cc = 0; cc < G; ++cc) wv.e[cc] = prev[k].e[cc] - c.e[cc];
+                wfn(s, k, pv, px, wv);
                 prev[k] = c;
             }
         }
         xlo = rlo; xhi = rhi; vlo = clo; vhi = chi;
     }
-    if (a.cout) {
-        T* co = a.cout + (long long)map * a.cout_stride;
+}
+
+template <typename T, int NT, int KV>
+__device__ __forceinline__ void load_owned(const T* A, const TileGeom& g,
+                                           VArr<T, Vec<T>::G> (&prev)[KV]) {
+    constexpr int G = Vec<T>::G;
 #pragma unroll
-        for (int k = 0; k < kPx; ++k) {
-            const int p = tid + k * NT;
-            if (p < npix) {
-                const int pv = p >> a.log_tw, px = p & twm;
-                co[(long long)((q + d0 * (v0 + pv)) & m) * n + x0 + px] = prev[k];
+    for (int k = 0; k < KV; ++k) {
+        const int p = threadIdx.x + k * NT;
+        if (p < g.nvec) {
+            const int e = p * G;
+            prev[k] = vload<T, G>(A + (g.Hv + (e >> g.log_tw)) * g.RS + g.Hx + (e & (g.tw - 1)));
+        }
+    }
+}
+
+template <typename T, int NT, int KV>
+__device__ __forceinline__ void store_owned(T* dst, const TileGeom& g,
+                                            const VArr<T, Vec<T>::G> (&val)[KV]) {
+    constexpr int G = Vec<T>::G;
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+        const int p = threadIdx.x + k * NT;
+        if (p < g.nvec) {
+            const int e = p * G;
+            const int pv = e >> g.log_tw, px = e & (g.tw - 1);
+            vstore<T, G>(dst + out_row(g, pv) + g.x0 + px, val[k]);
+        }
+    }
+}
+
+// Write mode: maps in gridDim.y; stores w_j and the stage's last c.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileGeom g = tile_geom(a.logn, a.j0, a.ns, a.log_tw, a.th, G);
+    const long long n2 = (long long)g.n * g.n;
+    T* A = reinterpret_cast<T*>(smem_raw) + G;  // element (v, i) at A[v*RS + i], i in [-G, TXT+G)
+    T* Bf = A + g.RS * g.TVT;
+    const int map = blockIdx.y;
+    const T* src = a.src + (long long)map * a.src_stride;
+    const int tvec = g.TXT / G;
+    for (int v = wave; v < g.TVT; v += NW) {
+        const long long row = tile_row(g, v);
+        for (int c = lane; c < tvec; c += 64)
+            vstore<T, G>(A + v * g.RS + c * G, vload<T, G>(src + row + ((g.x0 - g.Hx + c * G) & g.m)));
+    }
+    lds_barrier();
+    VA prev[kVecPerThread];
+    load_owned<T, NT, kVecPerThread>(A, g, prev);
+    T* planes = a.planes + (long long)map * a.planes_stride;
+    tile_scales<T, NT, kVecPerThread>(A, Bf, g, a.ns, prev, [&](int s, int, int pv, int px, const VA& w) {
+        vstore<T, G>(planes + (long long)(a.j0 + s - 1 - a.plane_base) * n2 + out_row(g, pv) + g.x0 + px, w);
+    });
+    if (a.cout) store_owned<T, NT, kVecPerThread>(a.cout + (long long)map * a.cout_stride, g, prev);
+}
+
+// Noise mode: each workgroup owns one tile and takes the realisations
+// b = group, group + groups, ... of the batch in turn, prefetching the next
+// realisation's tile into registers while the current one is processed.
+// Welford's running mean and sum of squared deviations of every owned pixel
+// and scale stay in registers; at the end they are merged (Chan's pairwise
+// update, double precision) into M, M2, or, with several groups, written as
+// float partials that k_merge_partials folds in group order.
+template <typename T>
+struct NoiseStageArgs {
+    int logn, j0, ns, log_tw, th;
+    const T* src;            // c_{j0-1} of realisation b at src + b*n^2
+    T* cout;                 // c_{j0+ns-1} of realisation b at cout + b*n^2, or null
+    int batch, groups, done;
+    double* M;               // [ns][n^2] running totals of the stage's scales
+    double* M2;
+    void* part;              // [groups][ns][2][n^2] partials (accumulator type) when groups > 1
+    float inv_tvec;          // 1 / (vectors per tile row), for index splitting
+};
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a) {
+    constexpr int KV = 1;  // one owned vector per thread keeps the Welford state small
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+    const TileGeom g = tile_geom(a.logn, a.j0, a.ns, a.log_tw, a.th, G);
+    const long long n2 = (long long)g.n * g.n;
+    T* A = reinterpret_cast<T*>(smem_raw) + G;
+    T* Bf = A + g.RS * g.TVT;
+    const int grp = blockIdx.y;
+    const int count = (a.batch - grp + a.groups - 1) / a.groups;
+    const int tvec = g.TXT / G;
+    const int nload = tvec * g.TVT;
+
+    VA pf[kPrefetch];
+    auto prefetch = [&](int b) {
+        const T* src = a.src + (long long)b * n2;
+#pragma unroll
+        for (int k = 0; k < kPrefetch; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if (e < nload) {
+                const int v = (int)(((float)e + 0.5f) * a.inv_tvec);
+                const int c = e - v * tvec;
+                pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + c * G) & g.m));
             }
         }
+    };
+    AccT mean[3][KV][G], m2[3][KV][G];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int k = 0; k < KV; ++k)
+#pragma unroll
+            for (int c = 0; c < G; ++c) mean[s][k][c] = m2[s][k][c] = (AccT)0;
+
+    if (count > 0) prefetch(grp);
+    for (int it = 0; it < count; ++it) {
+        const int b = grp + it * a.groups;
+        lds_barrier();  // the previous realisation is done with A and B
+#pragma unroll
+        for (int k = 0; k < kPrefetch; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if (e < nload) {
+                const int v = (int)(((float)e + 0.5f) * a.inv_tvec);
+                const int c = e - v * tvec;
+                vstore<T, G>(A + v * g.RS + c * G, pf[k]);
+            }
+        }
+        if (it + 1 < count) prefetch(b + a.groups);
+        lds_barrier();
+        VA prev[KV];
+        load_owned<T, NT, KV>(A, g, prev);
+        const AccT inv = (AccT)1 / (AccT)(it + 1);
+        tile_scales<T, NT, KV>(A, Bf, g, a.ns, prev, [&](int s, int k, int, int, const VA& w) {
+#pragma unroll
+            for (int ss = 0; ss < 3; ++ss) {  // static register indices
+                if (ss == s) {
+#pragma unroll
+                    for (int c = 0; c < G; ++c) {
+                        const AccT x = (AccT)w.e[c];
+                        const AccT d = x - mean[ss][k][c];
+                        mean[ss][k][c] = fma(d, inv, mean[ss][k][c]);
+                        m2[ss][k][c] = fma(d, x - mean[ss][k][c], m2[ss][k][c]);
+                    }
+                }
+            }
+        });
+        if (a.cout) store_owned<T, NT, KV>(a.cout + (long long)b * n2, g, prev);
+    }
+    // merge into the running totals, or leave float partials per group
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        if (s >= a.ns) break;
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            const int p = threadIdx.x + k * NT;
+            if (p >= g.nvec) continue;
+            const int e = p * G;
+            const long long base = out_row(g, e >> g.log_tw) + g.x0 + (e & (g.tw - 1));
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const long long gi = (long long)s * n2 + base + c;
+                if (a.groups == 1) {
+                    const double na = (double)a.done, nb = (double)count, nt = na + nb;
+                    const double delta = (double)mean[s][k][c] - a.M[gi];
+                    a.M[gi] += delta * (nb / nt);
+                    a.M2[gi] += (double)m2[s][k][c] + delta * delta * (na * nb / nt);
+                } else {
+                    AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * a.ns + s) * 2 * n2;
+                    pp[base + c] = mean[s][k][c];
+                    pp[n2 + base + c] = m2[s][k][c];
+                }
+            }
+        }
+    }
+}
+
+// Folds the per-group partials of one batch, in group order, into M, M2.
+template <typename P>
+__global__ void __launch_bounds__(256)
+k_merge_partials(const P* __restrict__ part, int groups, int ns, int batch, int done,
+                 long long n2, double* __restrict__ M, double* __restrict__ M2) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n2) return;
+    for (int s = 0; s < ns; ++s) {
+        double na = (double)done;
+        double mean = M[(long long)s * n2 + idx], m2 = M2[(long long)s * n2 + idx];
+        for (int grp = 0; grp < groups; ++grp) {
+            const double nb = (double)((batch - grp + groups - 1) / groups);
+            if (nb == 0.0) continue;
+            const P* pp = part + ((long long)grp * ns + s) * 2 * n2;
+            const double mb = (double)pp[idx], qb = (double)pp[n2 + idx];
+            const double nt = na + nb, delta = mb - mean;
+            mean += delta * (nb / nt);
+            m2 += qb + delta * delta * (na * nb / nt);
+            na = nt;
+        }
+        M[(long long)s * n2 + idx] = mean;
+        M2[(long long)s * n2 + idx] = m2;
     }
 }
 
@@ -233,9 +547,10 @@ constexpr double kMaxHaloRatio = 2.6;
 // overhead.  Returns false if no tile exists even for one scale.
 template <typename T>
 static bool pick_stage(int n, int j0, int left, StageGeom* g) {
+    constexpr int G = Vec<T>::G;
     const int d0 = 1 << (j0 - 1);
     for (int ns = left < 3 ? left : 3; ns >= 1; --ns) {
-        const int Hx = 2 * d0 * ((1 << ns) - 1), Hv = 2 * ((1 << ns) - 1);
+        const int Hx = stage_hx(d0, ns, G), Hv = 2 * ((1 << ns) - 1);
         bool found = false;
         StageGeom best{};
         double best_ratio = 0.0;
@@ -243,13 +558,15 @@ static bool pick_stage(int n, int j0, int left, StageGeom* g) {
             for (int th = 64; th >= 2; th /= 2) {
                 if (tw > n || th > n / d0) continue;
                 const int TXT = tw + 2 * Hx, TVT = th + 2 * Hv;
-                const size_t lds = 2 * (size_t)TXT * TVT * sizeof(T);
+                const size_t lds = 2 * (size_t)(TXT + 2 * G) * TVT * sizeof(T) + G * sizeof(T);
                 if (lds > (size_t)kLdsBytes) continue;
                 const double ratio = (double)TXT * TVT / ((double)tw * th);
                 if (ratio > kMaxHaloRatio && !(ns == 1 && ratio <= 2 * kMaxHaloRatio)) continue;
-                int nt = tw * th / kPx;
+                int nt = tw * th / (G * kVecPerThread);
                 nt = nt < 256 ? 256 : (nt > 512 ? 512 : nt);
-                if (tw * th > nt * kPx) continue;
+                if (tw * th > nt * G * kVecPerThread) continue;
+                if ((TXT / G) * TVT > nt * kPrefetch) continue;  // noise-mode prefetch
+                if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per noise thread
                 // prefer small overhead, then more workgroups per CU (less LDS)
                 if (!found || ratio < best_ratio - 1e-9 ||
                     (ratio < best_ratio + 1e-9 && lds < best.lds)) {
@@ -296,6 +613,52 @@ static hipError_t launch_stage(const StageArgs<T>& a, const StageGeom& g, int ma
         case 512: return launch_stage_nt<T, 512>(a, g, maps, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T, int NT>
+static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
+                                        hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
+                                    "noise_stage_j4", "noise_stage_j5", "noise_stage_j6",
+                                    "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
+                                    "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
+    AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                k_starlet_noise_stage<T, NT><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+    return hipGetLastError();
+}
+
+// Noise stages run one owned vector per thread: twice the write kernel's
+// threads per tile, at most 1024.
+static int noise_threads(const StageGeom& g, int G) {
+    int nt = g.tw * g.th / G;
+    return nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
+}
+
+template <typename T>
+static hipError_t launch_noise_stage(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
+                                     hipStream_t s) {
+    switch (noise_threads(g, Vec<T>::G)) {
+        case 256: return launch_noise_stage_nt<T, 256>(a, g, tiles, s);
+        case 512: return launch_noise_stage_nt<T, 512>(a, g, tiles, s);
+        case 1024: return launch_noise_stage_nt<T, 1024>(a, g, tiles, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Workgroups of a noise stage: one per tile, times enough realisation groups
+// to give every CU work (256 of them), at most one group per realisation.
+static int noise_groups(int tiles, int batch) {
+    int g = 256 / tiles;
+    if (g < 1) g = 1;
+    if (g > batch) g = batch;
+    return g;
 }
 
 // Per-scale path of one stage: c_in -> (w_j, c_out) through tmp, w_j at
@@ -347,6 +710,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     const long long final_stride = a.planes_stride;
     const T* cur = a.kappa;
     long long cur_stride = a.in_stride;
+    if (acc && a.in_stride != n2) return hipErrorInvalidValue;  // realisations are packed
     for (int gi = 0; gi < nstages; ++gi) {
         const Stage& st = plan[gi];
         const bool last = gi == nstages - 1;
@@ -365,10 +729,34 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         const long long wstride = acc ? 3 * n2 : a.planes_stride;
         const int pbase = acc ? st.j0 - 1 : 0;
         hipError_t e;
+        int lt = 0;
+        while ((1 << lt) < st.g.tw) ++lt;
+        if (st.tiled && acc) {
+            const int d0 = 1 << (st.j0 - 1);
+            const int tiles = (n / st.g.tw) * ((n / d0) / st.g.th) * d0;
+            NoiseStageArgs<T> s;
+            s.logn = a.logn; s.j0 = st.j0; s.ns = st.ns; s.log_tw = lt; s.th = st.g.th;
+            s.src = cur; s.cout = dst; s.batch = a.batch;
+            s.groups = noise_groups(tiles, a.batch); s.done = a.done;
+            s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
+            s.part = a.part;
+            s.inv_tvec = 1.0f / (float)((st.g.tw + 2 * stage_hx(d0, st.ns, Vec<T>::G)) / Vec<T>::G);
+            e = launch_noise_stage<T>(s, st.g, tiles, a.stream);
+            if (e == hipSuccess && s.groups > 1) {
+                using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+                AMAP_LAUNCH("merge_partials", a.stream,
+                            k_merge_partials<AccT><<<(unsigned)((n2 + 255) / 256), 256, 0, a.stream>>>(
+                                static_cast<const AccT*>(a.part), s.groups, st.ns, a.batch, a.done,
+                                n2, s.M, s.M2));
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) return e;
+            cur = dst;
+            cur_stride = dst_stride;
+            continue;
+        }
         if (st.tiled) {
             StageArgs<T> s;
-            int lt = 0;
-            while ((1 << lt) < st.g.tw) ++lt;
             s.logn = a.logn; s.j0 = st.j0; s.ns = st.ns; s.log_tw = lt; s.th = st.g.th;
             s.src = cur; s.src_stride = cur_stride;
             s.planes = wdst; s.planes_stride = wstride; s.plane_base = pbase;
@@ -393,6 +781,16 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         cur_stride = dst_stride;
     }
     return hipGetLastError();
+}
+
+// Groups x scales x (mean, M2) x pixels in the accumulator type, bounded by
+// 256 groups of the largest tile (4096 pixels) and by one group per
+// realisation.
+size_t starlet_partials_bytes(int logn, int batch) {
+    const long long n2 = 1ll << (2 * logn);
+    long long px = 256ll * 4096;
+    if ((long long)batch * n2 < px) px = (long long)batch * n2;
+    return (size_t)(3 * 2 * px) * sizeof(double);
 }
 
 template <typename T>
