@@ -17,23 +17,23 @@ struct cpx {
 };
 
 template <typename T>
-__device__ __forceinline__ cpx<T> make_cpx(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
+__host__ __device__ __forceinline__ cpx<T> make_cpx(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
 template <typename T>
-__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return make_cpx(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return make_cpx(a.x + b.x, a.y + b.y); }
 template <typename T>
-__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return make_cpx(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return make_cpx(a.x - b.x, a.y - b.y); }
 template <typename T>
-__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+__host__ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
     return make_cpx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // multiply by the conjugate of b
 template <typename T>
-__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+__host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
     return make_cpx(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 // multiply by -i (forward) or +i (inverse)
 template <typename T, bool INV>
-__device__ __forceinline__ cpx<T> rot90(cpx<T> a) {
+__host__ __device__ __forceinline__ cpx<T> rot90(cpx<T> a) {
     return INV ? make_cpx(-a.y, a.x) : make_cpx(a.y, -a.x);
 }
 

@@ -1,6 +1,6 @@
-// Kaiser-Squires inversion on the GPU: a two-dimensional complex FFT built
-// from LDS-resident Stockham radix-4 (+ one radix-2) passes, with the
-// spectral multiply by conj(D(k)) fused into the row pass.
+// Kaiser-Squires inversion on the GPU: a two-dimensional complex FFT with the
+// spectral multiply by conj(D(k)) fused between the forward and inverse
+// transforms along x.
 //
 // Pass structure for one n x n map (columns first, so that the row pass sees
 // whole spectral rows and can apply the KS kernel between its forward and
@@ -10,10 +10,20 @@
 //   P2  whole rows:     forward FFT along x, multiply by conj(D)/n^2,
 //                       inverse FFT along x                -> C
 //   P3  column strips:  inverse FFT along y -> kappa_E = Re, kappa_B = Im
-// A strip is W adjacent columns held in LDS at full height, so every HBM
-// access is a W-element row segment; a row pass holds whole rows.
+// A strip is W adjacent columns, so every HBM access is a W-element row
+// segment; a row pass reads and writes whole rows.
+//
+// Each length-N transform is a four-step FFT with N = N1 * N2: every thread
+// holds N1 (then N2) values in registers and runs a radix-2 DFT on them with
+// compile-time twiddles, the inter-step twiddles come from a table, and one
+// LDS exchange separates the two steps.  Along x a transform's N2 threads
+// sit in one wavefront, so the exchange needs no workgroup barrier, and the
+// inverse transform starts from the forward output exactly as each thread
+// holds it.  Sides whose per-thread DFTs would not fit in registers (float32
+// from 2048, float64 from 1024) use radix-4 Stockham passes held in LDS.
 #include "amap_device.h"
 #include "amap_launch.h"
+#include "fft_reg.h"
 
 namespace amap {
 
@@ -142,7 +152,7 @@ __device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i 
 // C + b*n*n.  Realisation index r = r0 + b.
 template <typename T, int LOGN, bool ROTATE>
 __global__ void __launch_bounds__((StripCfg<T, LOGN>::NT))
-k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
+k_ks_cols_fwd_generic(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
               cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0,
               const cpx<T>* __restrict__ tw) {
     using Cfg = StripCfg<T, LOGN>;
@@ -191,7 +201,7 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
 // ---- P2: rows: forward FFT along x, multiply by conj(D)/n^2, inverse ---------
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((RowCfg<T, LOGN>::NT))
-k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
+k_ks_rows_generic(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
     using Cfg = RowCfg<T, LOGN>;
     constexpr int N = Cfg::N, NT = Cfg::NT, ROWS = Cfg::ROWS;
     __shared__ cpx<T> buf[ROWS * N];
@@ -226,7 +236,7 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 // ---- P3: inverse FFT along y, split real/imaginary ---------------------------
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((StripCfg<T, LOGN>::NT))
-k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
+k_ks_cols_inv_generic(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
               long long out_stride, const cpx<T>* __restrict__ tw) {
     using Cfg = StripCfg<T, LOGN>;
     constexpr int N = Cfg::N, W = Cfg::W, NT = Cfg::NT;
@@ -250,25 +260,270 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
     }
 }
 
+// exp(-+2 pi i e / N) from the 4096-entry table
+template <typename T, int LOGN, bool INV>
+__device__ __forceinline__ cpx<T> table_twiddle(const cpx<T>* __restrict__ tw, int e) {
+    const cpx<T> w = tw[(e & ((1 << LOGN) - 1)) << (kMaxLogN - LOGN)];
+    return INV ? make_cpx(w.x, -w.y) : w;
+}
+
+// Four-step factors: N = N1 * N2, N1 = N2 or 2 N2.
+template <int LOGN>
+struct FS {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int N1 = 1 << ((LOGN + 1) / 2);
+    static constexpr int N2 = 1 << (LOGN / 2);
+    static constexpr int RR = N1 / N2;
+};
+
+// Threads and LDS of the four-step kernels
+template <typename T, int LOGN>
+struct Strip4 {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int W0 = ((128 * 1024) / (int)sizeof(cpx<T>)) / N;
+    static constexpr int W = W0 > 16 ? 16 : W0;
+    static constexpr int NT = W * FS<LOGN>::N2;
+};
+template <typename T, int LOGN>
+struct Row4 {
+    static constexpr int N2 = FS<LOGN>::N2, N1 = FS<LOGN>::N1;
+    static constexpr int N = 1 << LOGN;
+    static constexpr int NT = 128;
+    static constexpr int LINES0 = NT / N2 > 0 ? NT / N2 : 1;
+    static constexpr int LINES = LINES0 > N ? N : LINES0;
+    // exchange region per line: forward [N1][N2+1], inverse [N2][N1+1]
+    static constexpr int EX = (N1 * (N2 + 1)) > (N2 * (N1 + 1)) ? (N1 * (N2 + 1)) : (N2 * (N1 + 1));
+};
+
+// Orders the LDS accesses of one wavefront (the lanes of one transform).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// ---- P1: load shears (optionally rotate), forward FFT along y (four-step) -------
+template <typename T, int LOGN, bool ROTATE>
+__global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
+k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
+              cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0, const cpx<T>* __restrict__ tw) {
+    using F = FS<LOGN>;
+    using S = Strip4<T, LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W, NT = S::NT;
+    __shared__ cpx<T> buf[N * W];
+    const int b = blockIdx.y;
+    const int x0 = blockIdx.x * W;
+    const T* a1 = g1 + (long long)b * g_stride;
+    const T* a2 = g2 + (long long)b * g_stride;
+    if (ROTATE) {
+        // one Philox block covers 8 consecutive pixels of a row
+        constexpr int OCT_PER_ROW = (W + 7) / 8;
+        const uint64_t r = r0 + b;
+        for (int o = threadIdx.x; o < N * OCT_PER_ROW; o += NT) {
+            const int y = o / OCT_PER_ROW;
+            const int cx = (o % OCT_PER_ROW) * 8;
+            const int xa = (W >= 8) ? (x0 + cx) : (x0 & ~7);
+            const uint64_t pix = (uint64_t)y * N + xa;
+            uint32_t u[8];
+            philox_block_u32(seed, r, pix >> 3, u);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int x = xa + i;
+                if (W < 8 && (x < x0 || x >= x0 + W)) continue;
+                T p = a1[(long long)y * N + x], q = a2[(long long)y * N + x];
+                rotate_by_u32(u[i], p, q);
+                buf[y * W + (x - x0)] = make_cpx(p, q);
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < N * W; e += NT) {
+            const int y = e / W, c = e % W;
+            const long long gi = (long long)y * N + x0 + c;
+            buf[e] = make_cpx(a1[gi], a2[gi]);
+        }
+    }
+    __syncthreads();
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    cpx<T> a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = buf[(N2 * n1 + t) * W + c];
+    dft_reg<T, N1, false>(a);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], table_twiddle<T, LOGN, false>(tw, t * k1));
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * W + c] = a[k1];
+    __syncthreads();
+    cpx<T>* out = C + (long long)b * N * N + x0 + c;
+#pragma unroll
+    for (int r = 0; r < F::RR; ++r) {
+        const int k1 = t + N2 * r;
+        cpx<T> v[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(k1 * N2 + n2) * W + c];
+        dft_reg<T, N2, false>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) out[(long long)(k1 + N1 * k2) * N] = v[k2];
+    }
+}
+
+// ---- P2: rows: forward FFT along x, multiply by conj(D)/n^2, inverse (four-step) -
+template <typename T, int LOGN>
+__global__ void __launch_bounds__((Row4<T, LOGN>::NT))
+k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
+    using F = FS<LOGN>;
+    using R4 = Row4<T, LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR;
+    __shared__ cpx<T> ex[R4::LINES * R4::EX];
+    const int line = threadIdx.x / N2, t = threadIdx.x % N2;
+    if (line >= R4::LINES) return;  // no workgroup barrier follows
+    const int y = blockIdx.x * R4::LINES + line;
+    cpx<T>* row = C + (long long)blockIdx.y * N * N + (long long)y * N;
+    cpx<T>* E = ex + line * R4::EX;
+    // forward, step 1: DFT_N1 over n1 of x[N2 n1 + t]
+    cpx<T> a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = row[N2 * n1 + t];
+    dft_reg<T, N1, false>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        const cpx<T> v = k1 ? cmul(a[k1], table_twiddle<T, LOGN, false>(tw, t * k1)) : a[k1];
+        E[k1 * (N2 + 1) + t] = v;
+    }
+    wave_lds_sync();
+    // forward, step 2: DFT_N2 over n2 -> X[k1 + N1 k2], k1 = t + N2 r
+    cpx<T> b[RR][N2];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) b[r][n2] = E[(t + N2 * r) * (N2 + 1) + n2];
+        dft_reg<T, N2, false>(b[r]);
+    }
+    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2)
+    const T inv_n2 = (T)1 / ((T)N * (T)N);
+    const int m2 = signed_freq(y, N);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            const int m1 = signed_freq(t + N2 * r + N1 * k2, N);
+            const int den = m1 * m1 + m2 * m2;
+            cpx<T> v = b[r][k2];
+            if (den == 0) {
+                v = make_cpx((T)0, (T)0);
+            } else {
+                const bool nyq = (m1 == -N / 2) || (m2 == -N / 2);
+                const T dr = (T)(m1 * m1 - m2 * m2) / (T)den;
+                const T di = nyq ? (T)0 : (T)(2 * m1 * m2) / (T)den;
+                v = make_cpx((v.x * dr + v.y * di) * inv_n2, (v.y * dr - v.x * di) * inv_n2);
+            }
+            b[r][k2] = v;
+        }
+    }
+    wave_lds_sync();  // step-2 reads are done before the exchange is reused
+    // inverse, step 1: DFT_N2 over k2 for each k1 held, twiddle, exchange
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int k1 = t + N2 * r;
+        dft_reg<T, N2, true>(b[r]);
+#pragma unroll
+        for (int m = 0; m < N2; ++m) {
+            const cpx<T> v = m ? cmul(b[r][m], table_twiddle<T, LOGN, true>(tw, k1 * m)) : b[r][m];
+            E[m * (N1 + 1) + k1] = v;
+        }
+    }
+    wave_lds_sync();
+    // inverse, step 2: DFT_N1 over k1 for m = t -> x[t + N2 n]
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) a[k1] = E[t * (N1 + 1) + k1];
+    dft_reg<T, N1, true>(a);
+#pragma unroll
+    for (int n = 0; n < N1; ++n) row[t + N2 * n] = a[n];
+}
+
+// ---- P3: inverse FFT along y (four-step), split real/imaginary -----------------
+template <typename T, int LOGN>
+__global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
+k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
+              long long out_stride, const cpx<T>* __restrict__ tw) {
+    using F = FS<LOGN>;
+    using S = Strip4<T, LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W;
+    __shared__ cpx<T> buf[N * W];
+    const int b = blockIdx.y;
+    const int x0 = blockIdx.x * W;
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const cpx<T>* in = C + (long long)b * N * N + x0 + c;
+    cpx<T> a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = in[(long long)(N2 * n1 + t) * N];
+    dft_reg<T, N1, true>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        const cpx<T> v = k1 ? cmul(a[k1], table_twiddle<T, LOGN, true>(tw, t * k1)) : a[k1];
+        buf[(k1 * N2 + t) * W + c] = v;
+    }
+    __syncthreads();
+    T* oe = kE + (long long)b * out_stride + x0 + c;
+    T* ob = kB ? kB + (long long)b * out_stride + x0 + c : nullptr;
+#pragma unroll
+    for (int r = 0; r < F::RR; ++r) {
+        const int k1 = t + N2 * r;
+        cpx<T> v[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(k1 * N2 + n2) * W + c];
+        dft_reg<T, N2, true>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            const long long gi = (long long)(k1 + N1 * k2) * N;
+            oe[gi] = v[k2].x;
+            if (ob) ob[gi] = v[k2].y;
+        }
+    }
+}
+
 // ---- host launchers ------------------------------------------------------------
+// Transforms whose per-thread DFTs would spill registers (float32 from 2048,
+// float64 from 1024) keep their data in LDS.
+template <typename T, int LOGN>
+constexpr bool use_generic() { return sizeof(T) == 8 ? LOGN >= 10 : LOGN >= 11; }
+
 template <typename T, int LOGN>
 static hipError_t ks_launch_n(const KsArgs<T>& a) {
-    using S = StripCfg<T, LOGN>;
-    using R = RowCfg<T, LOGN>;
     constexpr int N = 1 << LOGN;
-    const dim3 gs(N / S::W, a.batch), gr(N / R::ROWS, a.batch);
-    if (a.rotate)
-        AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
-                    k_ks_cols_fwd<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
-                        a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
-    else
-        AMAP_LAUNCH("ks_cols_fwd", a.stream,
-                    k_ks_cols_fwd<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
-                        a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
-    AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
-    AMAP_LAUNCH("ks_cols_inv", a.stream,
-                k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB, a.out_stride,
-                                                                    a.tw));
+    if constexpr (use_generic<T, LOGN>()) {
+        using S = StripCfg<T, LOGN>;
+        using R = RowCfg<T, LOGN>;
+        const dim3 gs(N / S::W, a.batch), gr(N / R::ROWS, a.batch);
+        if (a.rotate)
+            AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
+                        k_ks_cols_fwd_generic<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
+                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+        else
+            AMAP_LAUNCH("ks_cols_fwd", a.stream,
+                        k_ks_cols_fwd_generic<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
+                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+        AMAP_LAUNCH("ks_rows", a.stream,
+                    k_ks_rows_generic<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
+        AMAP_LAUNCH("ks_cols_inv", a.stream,
+                    k_ks_cols_inv_generic<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
+                                                                                a.out_stride, a.tw));
+    } else {
+        using S = Strip4<T, LOGN>;
+        using R = Row4<T, LOGN>;
+        const dim3 gs(N / S::W, a.batch), gr(N / R::LINES, a.batch);
+        if (a.rotate)
+            AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
+                        k_ks_cols_fwd<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
+                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+        else
+            AMAP_LAUNCH("ks_cols_fwd", a.stream,
+                        k_ks_cols_fwd<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
+                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+        AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
+        AMAP_LAUNCH("ks_cols_inv", a.stream,
+                    k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
+                                                                        a.out_stride, a.tw));
+    }
     return hipGetLastError();
 }
 
