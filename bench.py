@@ -98,7 +98,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle's timed sample (0 to skip)")
-    ap.add_argument("--kernel-timing", action="store_true", default=True)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the "
@@ -127,6 +129,12 @@ def main():
     def step():
         ctx.run_path(t1, t2, J, R_REAL, SEED, THRESH, out=out)
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -155,7 +163,7 @@ def main():
     torch.cuda.synchronize()
     ktimes = ctx.timing_read(reset=True)
     ctx.timing_enable(False)
-    B = min(R_REAL, max(1, (1 << 24) // (N * N)))
+    B = min(R_REAL, max(1, (1 << 25) // (N * N)))
     kernels = {}
     for name, (launches, tot_ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
         kernels[name] = {"launches_per_step": launches / args.steps,

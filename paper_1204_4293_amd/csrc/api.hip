@@ -293,7 +293,7 @@ amap_status enqueue_starlet(int logn, int J, int batch, const T* kappa, long lon
 // Realisations per launch sequence of the noise loop.
 int noise_batch(int n, int n_real) {
     const long long n2 = (long long)n * n;
-    long long b = (1ll << 24) / n2;  // ~16 M pixels of realisations in flight
+    long long b = (1ll << 25) / n2;  // ~32 M pixels of realisations in flight
     if (b < 1) b = 1;
     if (b > n_real) b = n_real;
     return (int)b;

@@ -53,25 +53,32 @@ struct StageArgs {
 
 // 16-byte vectors: four floats or two doubles
 template <typename T> struct Vec;
-template <> struct Vec<float> { using type = float4; static constexpr int G = 4; };
-template <> struct Vec<double> { using type = double2; static constexpr int G = 2; };
+template <> struct Vec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int G = 4;
+};
+template <> struct Vec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int G = 2;
+};
 
 template <typename T, int G>
 struct VArr { T e[G]; };
 
+// 16-byte loads and stores of G consecutive values (p is 16-byte aligned).
 template <typename T, int G>
 __device__ __forceinline__ VArr<T, G> vload(const T* p) {
     const typename Vec<T>::type v = *reinterpret_cast<const typename Vec<T>::type*>(p);
     VArr<T, G> r;
-    if constexpr (G == 4) { r.e[0] = v.x; r.e[1] = v.y; r.e[2] = v.z; r.e[3] = v.w; }
-    else { r.e[0] = v.x; r.e[1] = v.y; }
+#pragma unroll
+    for (int c = 0; c < G; ++c) r.e[c] = v[c];
     return r;
 }
 template <typename T, int G>
 __device__ __forceinline__ void vstore(T* p, const VArr<T, G>& r) {
     typename Vec<T>::type v;
-    if constexpr (G == 4) { v.x = r.e[0]; v.y = r.e[1]; v.z = r.e[2]; v.w = r.e[3]; }
-    else { v.x = r.e[0]; v.y = r.e[1]; }
+#pragma unroll
+    for (int c = 0; c < G; ++c) v[c] = r.e[c];
     *reinterpret_cast<typename Vec<T>::type*>(p) = v;
 }
 template <typename T, int G>
@@ -96,6 +103,11 @@ __host__ __device__ inline int stage_hx(int d0, int ns, int G) {
 constexpr int kSegLen = 4;        // column-pass outputs per sliding window
 constexpr int kVecPerThread = 2;  // owned output vectors per thread
 constexpr int kPrefetch = 6;      // tile vectors per thread held while prefetching
+
+// Prefetch registers of a noise-stage thread.  The planner bounds a tile's
+// vectors by 6 per write-kernel thread (at most 512 threads), so 1024-thread
+// noise stages need only 3, which keeps them within 128 VGPRs.
+__host__ __device__ constexpr int noise_prefetch(int nt) { return nt >= 1024 ? 3 : kPrefetch; }
 
 // Barrier that orders only LDS accesses, so global loads issued before it
 // (the next tile's prefetch) stay in flight across it.
@@ -147,111 +159,101 @@ __device__ __forceinline__ int fdiv(int e, float inv_d) {
     return (int)(((float)e + 0.5f) * inv_d);
 }
 
-// Runs the ns scales of a stage on the tile in A (B is scratch).  prev holds
-// c_{j0-1} of the owned vectors on entry and the stage's last c on exit;
-// wfn(s, k, pv, px, w) receives w_{j0+s} of owned vector k.  Work items are
-// (row, vector) pairs spread over all threads; each thread takes two row
-// items at a time so their LDS reads overlap.
-template <typename T, int NT, int KV, typename WFn>
-__device__ __forceinline__ void tile_scales(T* A, T* Bf, const TileGeom& g, int ns,
-                                            VArr<T, Vec<T>::G> (&prev)[KV], WFn wfn) {
+// Row and column passes of scale s of a stage on the tile in A (B is
+// scratch); on return A holds c_{j0+s} on the shrunken valid region
+// [xlo, xhi) x [vlo, vhi), which the call updates.  Work items are (row,
+// vector) pairs spread over all threads; each thread takes two row items at
+// a time so their LDS reads overlap.
+template <typename T, int NT>
+__device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, int s, int& xlo,
+                                                int& xhi, int& vlo, int& vhi) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
     const int tid = threadIdx.x;
-    const int RS = g.RS, twm = g.tw - 1;
-    int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
-    for (int s = 0; s < ns; ++s) {
-        const int dx = g.d0 << s, dv = 1 << s;
-        // row pass A -> B over rows [vlo, vhi), outputs [rlo, rhi) widened to
-        // whole vectors (the extra outputs stay outside the valid region)
-        const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
-        const int rlo4 = rlo / G * G;
-        const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
-        const float inv_nv = 1.0f / (float)nv;
-        const int rtot = nv * (vhi - vlo);
-        for (int e0 = tid; e0 < rtot; e0 += 2 * NT) {
-            VA o[2];
-            int off[2];
+    const int RS = g.RS;
+    const int dx = g.d0 << s, dv = 1 << s;
+    // row pass A -> B over rows [vlo, vhi), outputs [rlo, rhi) widened to
+    // whole vectors (the extra outputs stay outside the valid region)
+    const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
+    const int rlo4 = rlo / G * G;
+    const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
+    const float inv_nv = 1.0f / (float)nv;
+    const int rtot = nv * (vhi - vlo);
+    for (int e0 = tid; e0 < rtot; e0 += 2 * NT) {
+        VA o[2];
+        int off[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0 + u * NT;
-                off[u] = -1;
-                if (e < rtot) {
-                    const int r = fdiv(e, inv_nv);
-                    const int i0 = rlo4 + (e - r * nv) * G;
-                    const T* ra = A + (vlo + r) * RS;
-                    off[u] = (vlo + r) * RS + i0;
-                    if (2 * dx <= G) {  // the five taps of all G outputs lie in three vectors
-                        const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
-                                 rr = vload<T, G>(ra + i0 + G);
-                        T w[3 * G];
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * NT;
+            off[u] = -1;
+            if (e < rtot) {
+                const int r = fdiv(e, inv_nv);
+                const int i0 = rlo4 + (e - r * nv) * G;
+                const T* ra = A + (vlo + r) * RS;
+                off[u] = (vlo + r) * RS + i0;
+                if (2 * dx <= G) {  // the five taps of all G outputs lie in three vectors
+                    const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
+                             rr = vload<T, G>(ra + i0 + G);
+                    T w[3 * G];
 #pragma unroll
-                        for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
+                    for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
 #pragma unroll
-                        for (int k = 0; k < G; ++k) {
-                            const int b = G + k;
-                            o[u].e[k] = dx == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
-                                                : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
-                                                             w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
-                        }
-                    } else {  // dilation is a multiple of the vector width
-                        o[u] = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
-                                              vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
-                                              vload<T, G>(ra + i0 + 2 * dx));
+                    for (int k = 0; k < G; ++k) {
+                        const int b = G + k;
+                        o[u].e[k] = dx == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
+                                            : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
+                                                         w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
                     }
+                } else {  // dilation is a multiple of the vector width
+                    o[u] = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
+                                          vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
+                                          vload<T, G>(ra + i0 + 2 * dx));
                 }
             }
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (off[u] >= 0) vstore<T, G>(Bf + off[u], o[u]);
         }
-        lds_barrier();
-        // column pass B -> A: windows of kSegLen outputs along each chain
-        // v = clo + phase + dv*t, one vector column per item; all window
-        // values are read before any output is written
-        const int clo = vlo + 2 * dv, chi = vhi - 2 * dv;
-        const int lmax = (chi - clo + dv - 1) / dv;
-        const int nseg = (lmax + kSegLen - 1) / kSegLen;
-        const int items = nv * dv * nseg;
-        for (int it = tid; it < items; it += NT) {
-            const int r = fdiv(it, inv_nv);
-            const int i0 = rlo4 + (it - r * nv) * G;
-            const int phase = r & (dv - 1), seg = r >> s;
-            const int vfirst = clo + phase + dv * (seg * kSegLen);
-            if (vfirst >= chi) continue;
-            const T* col = Bf + i0;
-            VA win[kSegLen + 4];
 #pragma unroll
-            for (int k = 0; k < kSegLen + 4; ++k) {
-                const int v = vfirst + dv * (k - 2);
-                if (k < 4 || v < chi + 2 * dv) win[k] = vload<T, G>(col + v * RS);
-            }
-#pragma unroll
-            for (int k = 0; k < kSegLen; ++k) {
-                const int v = vfirst + dv * k;
-                if (v < chi)
-                    vstore<T, G>(A + v * RS + i0,
-                                 vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
-            }
-        }
-        lds_barrier();
-        // w of the owned vectors (the next row pass only reads A)
-#pragma unroll
-        for (int k = 0; k < KV; ++k) {
-            const int p = tid + k * NT;
-            if (p < g.nvec) {
-                const int e = p * G;
-                const int pv = e >> g.log_tw, px = e & twm;
-                const VA c = vload<T, G>(A + (g.Hv + pv) * RS + g.Hx + px);
-                VA wv;
-#pragma unroll
-                for (int cc = 0; cc < G; ++cc) wv.e[cc] = prev[k].e[cc] - c.e[cc];
-                wfn(s, k, pv, px, wv);
-                prev[k] = c;
-            }
-        }
-        xlo = rlo; xhi = rhi; vlo = clo; vhi = chi;
+        for (int u = 0; u < 2; ++u)
+            if (off[u] >= 0) vstore<T, G>(Bf + off[u], o[u]);
     }
+    lds_barrier();
+    // column pass B -> A: windows of kSegLen outputs along each chain
+    // v = clo + phase + dv*t, one vector column per item; all window
+    // values are read before any output is written
+    const int clo = vlo + 2 * dv, chi = vhi - 2 * dv;
+    const int lmax = (chi - clo + dv - 1) / dv;
+    const int nseg = (lmax + kSegLen - 1) / kSegLen;
+    const int items = nv * dv * nseg;
+    for (int it = tid; it < items; it += NT) {
+        const int r = fdiv(it, inv_nv);
+        const int i0 = rlo4 + (it - r * nv) * G;
+        const int phase = r & (dv - 1), seg = r >> s;
+        const int vfirst = clo + phase + dv * (seg * kSegLen);
+        if (vfirst >= chi) continue;
+        const T* col = Bf + i0;
+        VA win[kSegLen + 4];
+#pragma unroll
+        for (int k = 0; k < kSegLen + 4; ++k) {
+            const int v = vfirst + dv * (k - 2);
+            if (k < 4 || v < chi + 2 * dv) win[k] = vload<T, G>(col + v * RS);
+        }
+#pragma unroll
+        for (int k = 0; k < kSegLen; ++k) {
+            const int v = vfirst + dv * k;
+            if (v < chi)
+                vstore<T, G>(A + v * RS + i0,
+                             vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+        }
+    }
+    lds_barrier();
+    xlo = rlo; xhi = rhi; vlo = clo; vhi = chi;
+}
+
+// Owned vector k of the tile: its LDS offset and global offset in a plane.
+__device__ __forceinline__ int owned_lds(const TileGeom& g, int e) {
+    return (g.Hv + (e >> g.log_tw)) * g.RS + g.Hx + (e & (g.tw - 1));
+}
+__device__ __forceinline__ long long owned_global(const TileGeom& g, int e) {
+    return out_row(g, e >> g.log_tw) + g.x0 + (e & (g.tw - 1));
 }
 
 template <typename T, int NT, int KV>
@@ -307,9 +309,24 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
     VA prev[kVecPerThread];
     load_owned<T, NT, kVecPerThread>(A, g, prev);
     T* planes = a.planes + (long long)map * a.planes_stride;
-    tile_scales<T, NT, kVecPerThread>(A, Bf, g, a.ns, prev, [&](int s, int, int pv, int px, const VA& w) {
-        vstore<T, G>(planes + (long long)(a.j0 + s - 1 - a.plane_base) * n2 + out_row(g, pv) + g.x0 + px, w);
-    });
+    int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
+    for (int s = 0; s < a.ns; ++s) {
+        tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
+        // w of the owned vectors (the next row pass only reads A)
+        T* wp = planes + (long long)(a.j0 + s - 1 - a.plane_base) * n2;
+#pragma unroll
+        for (int k = 0; k < kVecPerThread; ++k) {
+            const int p = threadIdx.x + k * NT;
+            if (p < g.nvec) {
+                const VA c = vload<T, G>(A + owned_lds(g, p * G));
+                VA wv;
+#pragma unroll
+                for (int cc = 0; cc < G; ++cc) wv.e[cc] = prev[k].e[cc] - c.e[cc];
+                vstore<T, G>(wp + owned_global(g, p * G), wv);
+                prev[k] = c;
+            }
+        }
+    }
     if (a.cout) store_owned<T, NT, kVecPerThread>(a.cout + (long long)map * a.cout_stride, g, prev);
 }
 
@@ -334,7 +351,6 @@ struct NoiseStageArgs {
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a) {
-    constexpr int KV = 1;  // one owned vector per thread keeps the Welford state small
     extern __shared__ unsigned char smem_raw[];
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
@@ -348,84 +364,91 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
     const int tvec = g.TXT / G;
     const int nload = tvec * g.TVT;
 
-    VA pf[kPrefetch];
-    auto prefetch = [&](int b) {
-        const T* src = a.src + (long long)b * n2;
-#pragma unroll
-        for (int k = 0; k < kPrefetch; ++k) {
-            const int e = threadIdx.x + k * NT;
-            if (e < nload) {
-                const int v = (int)(((float)e + 0.5f) * a.inv_tvec);
-                const int c = e - v * tvec;
-                pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + c * G) & g.m));
-            }
-        }
-    };
-    AccT mean[3][KV][G], m2[3][KV][G];
+    constexpr int PF = noise_prefetch(NT);
+    VA pf[PF];
+    AccT mean[3][G], m2[3][G];
 #pragma unroll
     for (int s = 0; s < 3; ++s)
 #pragma unroll
-        for (int k = 0; k < KV; ++k)
-#pragma unroll
-            for (int c = 0; c < G; ++c) mean[s][k][c] = m2[s][k][c] = (AccT)0;
+        for (int c = 0; c < G; ++c) mean[s][c] = m2[s][c] = (AccT)0;
+    const bool owner = (int)threadIdx.x < g.nvec;
+    const int own_e = threadIdx.x * G;
 
-    if (count > 0) prefetch(grp);
+    // first tile
+    if (count > 0) {
+        const T* src = a.src + (long long)grp * n2;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if (e < nload) {
+                const int v = fdiv(e, a.inv_tvec);
+                pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + (e - v * tvec) * G) & g.m));
+            }
+        }
+    }
     for (int it = 0; it < count; ++it) {
         const int b = grp + it * a.groups;
         lds_barrier();  // the previous realisation is done with A and B
 #pragma unroll
-        for (int k = 0; k < kPrefetch; ++k) {
+        for (int k = 0; k < PF; ++k) {
             const int e = threadIdx.x + k * NT;
             if (e < nload) {
-                const int v = (int)(((float)e + 0.5f) * a.inv_tvec);
-                const int c = e - v * tvec;
-                vstore<T, G>(A + v * g.RS + c * G, pf[k]);
+                const int v = fdiv(e, a.inv_tvec);
+                vstore<T, G>(A + v * g.RS + (e - v * tvec) * G, pf[k]);
             }
         }
-        if (it + 1 < count) prefetch(b + a.groups);
-        lds_barrier();
-        VA prev[KV];
-        load_owned<T, NT, KV>(A, g, prev);
-        const AccT inv = (AccT)1 / (AccT)(it + 1);
-        tile_scales<T, NT, KV>(A, Bf, g, a.ns, prev, [&](int s, int k, int, int, const VA& w) {
+        if (it + 1 < count) {  // prefetch the next realisation's tile
+            const T* src = a.src + (long long)(b + a.groups) * n2;
 #pragma unroll
-            for (int ss = 0; ss < 3; ++ss) {  // static register indices
-                if (ss == s) {
-#pragma unroll
-                    for (int c = 0; c < G; ++c) {
-                        const AccT x = (AccT)w.e[c];
-                        const AccT d = x - mean[ss][k][c];
-                        mean[ss][k][c] = fma(d, inv, mean[ss][k][c]);
-                        m2[ss][k][c] = fma(d, x - mean[ss][k][c], m2[ss][k][c]);
-                    }
+            for (int k = 0; k < PF; ++k) {
+                const int e = threadIdx.x + k * NT;
+                if (e < nload) {
+                    const int v = fdiv(e, a.inv_tvec);
+                    pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + (e - v * tvec) * G) & g.m));
                 }
             }
-        });
-        if (a.cout) store_owned<T, NT, KV>(a.cout + (long long)b * n2, g, prev);
+        }
+        lds_barrier();
+        VA prev;
+        if (owner) prev = vload<T, G>(A + owned_lds(g, own_e));
+        const AccT inv = (AccT)1 / (AccT)(it + 1);
+        int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {  // unrolled: the Welford state keeps static indices
+            if (s >= a.ns) break;
+            tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
+            if (owner) {
+                const VA c = vload<T, G>(A + owned_lds(g, own_e));
+#pragma unroll
+                for (int cc = 0; cc < G; ++cc) {
+                    const AccT x = (AccT)(prev.e[cc] - c.e[cc]);
+                    const AccT d = x - mean[s][cc];
+                    mean[s][cc] = fma(d, inv, mean[s][cc]);
+                    m2[s][cc] = fma(d, x - mean[s][cc], m2[s][cc]);
+                }
+                prev = c;
+            }
+        }
+        if (a.cout && owner) vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e), prev);
     }
-    // merge into the running totals, or leave float partials per group
+    // merge into the running totals, or leave partials per group
+    if (!owner) return;
+    const long long base = owned_global(g, own_e);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         if (s >= a.ns) break;
 #pragma unroll
-        for (int k = 0; k < KV; ++k) {
-            const int p = threadIdx.x + k * NT;
-            if (p >= g.nvec) continue;
-            const int e = p * G;
-            const long long base = out_row(g, e >> g.log_tw) + g.x0 + (e & (g.tw - 1));
-#pragma unroll
-            for (int c = 0; c < G; ++c) {
-                const long long gi = (long long)s * n2 + base + c;
-                if (a.groups == 1) {
-                    const double na = (double)a.done, nb = (double)count, nt = na + nb;
-                    const double delta = (double)mean[s][k][c] - a.M[gi];
-                    a.M[gi] += delta * (nb / nt);
-                    a.M2[gi] += (double)m2[s][k][c] + delta * delta * (na * nb / nt);
-                } else {
-                    AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * a.ns + s) * 2 * n2;
-                    pp[base + c] = mean[s][k][c];
-                    pp[n2 + base + c] = m2[s][k][c];
-                }
+        for (int c = 0; c < G; ++c) {
+            const long long gi = (long long)s * n2 + base + c;
+            if (a.groups == 1) {
+                const double na = (double)a.done, nb = (double)count, nt = na + nb;
+                const double delta = (double)mean[s][c] - a.M[gi];
+                a.M[gi] += delta * (nb / nt);
+                a.M2[gi] += (double)m2[s][c] + delta * delta * (na * nb / nt);
+            } else {
+                AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * a.ns + s) * 2 * n2;
+                pp[base + c] = mean[s][c];
+                pp[n2 + base + c] = m2[s][c];
             }
         }
     }
@@ -624,6 +647,13 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
+    }
+    {  // the tile must fit the prefetch registers and the owned vectors the threads
+        constexpr int G = Vec<T>::G;
+        const int d0 = 1 << (a.j0 - 1);
+        const int TXT = g.tw + 2 * stage_hx(d0, a.ns, G), TVT = g.th + 2 * 2 * ((1 << a.ns) - 1);
+        if ((TXT / G) * TVT > NT * noise_prefetch(NT) || g.tw * g.th > NT * G)
+            return hipErrorInvalidConfiguration;
     }
     static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
                                     "noise_stage_j4", "noise_stage_j5", "noise_stage_j6",
