@@ -146,6 +146,11 @@ struct RowCfg {
 
 __device__ __forceinline__ int signed_freq(int i, int n) { return i < n / 2 ? i : i - n; }
 
+// Reciprocal: the hardware estimate (1 ulp) in single precision, a rounded
+// division in double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // ---- P1: load shears (optionally rotate), forward FFT along y -------------------
 // grid: (n / W strips, batch).  Map b reads g1 + b*g_stride (g_stride = 0 when
 // every batch entry is a noise realisation of the same map) and writes
@@ -267,6 +272,27 @@ __device__ __forceinline__ cpx<T> table_twiddle(const cpx<T>* __restrict__ tw, i
     return INV ? make_cpx(w.x, -w.y) : w;
 }
 
+// exp(-+2 pi i base k / N) for k = 1 .. K-1, passed to f(k, w) in increasing
+// k: five table reads (base times 1, 2, 4, 8, 16) and one complex product
+// per power, w(k) = w(k without its lowest set bit) * w(lowest set bit), so
+// each power carries at most four roundings and only a few are live at once.
+template <typename T, int LOGN, bool INV, int K, typename Fn>
+__device__ __forceinline__ void twiddle_powers(const cpx<T>* __restrict__ tw, int base, Fn&& f) {
+    static_assert(K <= 64, "at most 64 powers");
+    constexpr int NB = K <= 2 ? 1 : (K <= 4 ? 2 : (K <= 8 ? 3 : (K <= 16 ? 4 : (K <= 32 ? 5 : 6))));
+    cpx<T> p[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) p[b] = table_twiddle<T, LOGN, INV>(tw, base << b);
+    cpx<T> w[K];
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        const int low = k & -k, rest = k - low;
+        const int bit = __builtin_ctz(low);
+        w[k] = rest ? cmul(w[rest], p[bit]) : p[bit];
+        f(k, w[k]);
+    }
+}
+
 // Four-step factors: N = N1 * N2, N1 = N2 or 2 N2.
 template <int LOGN>
 struct FS {
@@ -347,8 +373,7 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = buf[(N2 * n1 + t) * W + c];
     dft_reg<T, N1, false>(a);
-#pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], table_twiddle<T, LOGN, false>(tw, t * k1));
+    twiddle_powers<T, LOGN, false, N1>(tw, t, [&](int k1, const cpx<T>& w) { a[k1] = cmul(a[k1], w); });
     __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * W + c] = a[k1];
@@ -384,11 +409,10 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = row[N2 * n1 + t];
     dft_reg<T, N1, false>(a);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-        const cpx<T> v = k1 ? cmul(a[k1], table_twiddle<T, LOGN, false>(tw, t * k1)) : a[k1];
-        E[k1 * (N2 + 1) + t] = v;
-    }
+    E[t] = a[0];
+    twiddle_powers<T, LOGN, false, N1>(tw, t, [&](int k1, const cpx<T>& w) {
+        E[k1 * (N2 + 1) + t] = cmul(a[k1], w);
+    });
     wave_lds_sync();
     // forward, step 2: DFT_N2 over n2 -> X[k1 + N1 k2], k1 = t + N2 r
     cpx<T> b[RR][N2];
@@ -398,7 +422,8 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
         for (int n2 = 0; n2 < N2; ++n2) b[r][n2] = E[(t + N2 * r) * (N2 + 1) + n2];
         dft_reg<T, N2, false>(b[r]);
     }
-    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2)
+    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2);
+    // the integer numerators and denominator are exact in T (|m| <= n/2)
     const T inv_n2 = (T)1 / ((T)N * (T)N);
     const int m2 = signed_freq(y, N);
 #pragma unroll
@@ -407,16 +432,12 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
         for (int k2 = 0; k2 < N2; ++k2) {
             const int m1 = signed_freq(t + N2 * r + N1 * k2, N);
             const int den = m1 * m1 + m2 * m2;
-            cpx<T> v = b[r][k2];
-            if (den == 0) {
-                v = make_cpx((T)0, (T)0);
-            } else {
-                const bool nyq = (m1 == -N / 2) || (m2 == -N / 2);
-                const T dr = (T)(m1 * m1 - m2 * m2) / (T)den;
-                const T di = nyq ? (T)0 : (T)(2 * m1 * m2) / (T)den;
-                v = make_cpx((v.x * dr + v.y * di) * inv_n2, (v.y * dr - v.x * di) * inv_n2);
-            }
-            b[r][k2] = v;
+            const bool nyq = (m1 == -N / 2) || (m2 == -N / 2);
+            const T s = den ? inv_n2 * recip((T)den) : (T)0;  // D(0) = 0
+            const T dr = (T)(m1 * m1 - m2 * m2) * s;
+            const T di = nyq ? (T)0 : (T)(2 * m1 * m2) * s;
+            const cpx<T> v = b[r][k2];
+            b[r][k2] = make_cpx(v.x * dr + v.y * di, v.y * dr - v.x * di);
         }
     }
     wave_lds_sync();  // step-2 reads are done before the exchange is reused
@@ -425,11 +446,10 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
     for (int r = 0; r < RR; ++r) {
         const int k1 = t + N2 * r;
         dft_reg<T, N2, true>(b[r]);
-#pragma unroll
-        for (int m = 0; m < N2; ++m) {
-            const cpx<T> v = m ? cmul(b[r][m], table_twiddle<T, LOGN, true>(tw, k1 * m)) : b[r][m];
-            E[m * (N1 + 1) + k1] = v;
-        }
+        E[k1] = b[r][0];
+        twiddle_powers<T, LOGN, true, N2>(tw, k1, [&](int m, const cpx<T>& w) {
+            E[m * (N1 + 1) + k1] = cmul(b[r][m], w);
+        });
     }
     wave_lds_sync();
     // inverse, step 2: DFT_N1 over k1 for m = t -> x[t + N2 n]
@@ -457,11 +477,10 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = in[(long long)(N2 * n1 + t) * N];
     dft_reg<T, N1, true>(a);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-        const cpx<T> v = k1 ? cmul(a[k1], table_twiddle<T, LOGN, true>(tw, t * k1)) : a[k1];
-        buf[(k1 * N2 + t) * W + c] = v;
-    }
+    buf[t * W + c] = a[0];
+    twiddle_powers<T, LOGN, true, N1>(tw, t, [&](int k1, const cpx<T>& w) {
+        buf[(k1 * N2 + t) * W + c] = cmul(a[k1], w);
+    });
     __syncthreads();
     T* oe = kE + (long long)b * out_stride + x0 + c;
     T* ob = kB ? kB + (long long)b * out_stride + x0 + c : nullptr;
