@@ -11,6 +11,8 @@ every noise realisation, each producing J planes of N^2 pixels.
 
 Printed as one JSON line.  Extra objects:
   plain        one map through KS + starlet, one launch sequence per map
+  batched      512 uneven maps (KS + starlet) as one grouped, graph-captured
+               plan, and the same maps one launch sequence per map
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -31,10 +33,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
 N, J, R_REAL, SEED, THRESH = 1024, 7, 256, 23, 3.0
+TRAFFIC_PROFILE = "noise_path_1024_J7_R256_traffic.md"
 GRF_SEED, NOISE_SEED = 11, 12
 
 
-def kernel_model(name, n, J, batch_real):
+def kernel_model(name, n, J, batch_real, stage_starts=()):
     """Algorithmic bytes and flops of one launch of each kernel (float32).
 
     bytes: the kernel's compulsory input + output, each operand read or
@@ -43,26 +46,65 @@ def kernel_model(name, n, J, batch_real):
     flops: 5 m log2 m per length-m complex FFT, 6 per complex multiply,
     19 per pixel and starlet scale (two 5-tap B3 filters and a difference),
     4 per pixel and scale for the running mean and squared deviation.
+    ``stage_starts`` lists the first scale of each noise stage (from the
+    kernel names), which fixes how many scales a stage covers.
     """
     n2 = float(n * n)
     lg = n.bit_length() - 1
     B = batch_real
     fft1d = 5.0 * n2 * lg  # n transforms of length n
-    scales_last = (J - 1) - 3 * ((J - 2) // 3)  # scales in the last stage
     models = {
         "ks_cols_fwd_rotate": (8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 6.0 * n2)),
         "ks_cols_fwd": (16.0 * n2, fft1d),
         "ks_rows": (16.0 * n2 * B, B * (2 * fft1d + 6.0 * n2)),
         "ks_cols_inv": (12.0 * n2 * B, B * fft1d),
-        "noise_stage_j1": ((8.0 * B + 96.0) * n2, 3 * (19.0 + 4.0) * n2 * B),
-        "noise_stage_j4": ((4.0 * B + 32.0 * scales_last) * n2,
-                           scales_last * (19.0 + 4.0) * n2 * B),
-        "starlet_stage_j1": (20.0 * n2, 3 * 19.0 * n2),
-        "starlet_stage_j4": ((8.0 + 4.0 * scales_last) * n2, scales_last * 19.0 * n2),
         "noise_finalize": ((16.0 + 12.0) * (J - 1) * n2, 3.0 * (J - 1) * n2),
         "count_peaks": (4.0 * (J - 1) * n2, 9.0 * (J - 1) * n2),
     }
+    starts = sorted(stage_starts)
+    for i, j0 in enumerate(starts):
+        last = i + 1 == len(starts)
+        ns = (J - j0) if last else starts[i + 1] - j0
+        # read c_{j0-1}, write c_{j0+ns-1} unless last, M and M2 of ns scales
+        rd = 4.0 * B * n2 + 16.0 * ns * n2
+        wr = (0.0 if last else 4.0 * B * n2) + 16.0 * ns * n2
+        models["noise_stage_j%d" % j0] = (rd + wr, ns * (19.0 + 4.0) * n2 * B)
+        # the signal's write-mode stage: read c, write ns planes and the last c
+        models["starlet_stage_j%d" % j0] = ((4.0 + 4.0 * ns + 4.0) * n2, ns * 19.0 * n2)
     return models.get(name, (None, None))
+
+
+def kernel_sources_sha256():
+    """Digest of the library's kernel sources; a stored counter summary is
+    only used while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1204_4293_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (each counter scaled by its reading for
+    a copy of known size), or None when that summary was taken on other
+    kernel sources or does not cover the kernel."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    sha, table = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("kernel-sources-sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("traffic-json:"):
+                table = json.loads(line.split(":", 1)[1])
+    if sha != kernel_sources_sha256() or not table or kernel not in table:
+        return None
+    return table[kernel]["bytes_per_launch"]
 
 
 def cpu_baseline(g1, g2, budget_s):
@@ -89,6 +131,75 @@ def cpu_baseline(g1, g2, budget_s):
             "sample": "the 1024x1024 map: KS + starlet (J=7) of the signal and %d noise "
                       "realisations with sigma, S/N and peaks, %.1f s" % (r, total),
             "cpu": platform.processor() or platform.machine()}
+
+
+def uneven_batch(ctx, reps):
+    """The uneven batch: 512 float32 maps, sides drawn from {128..2048}
+    (weights 4:4:3:2:1, seed 31), J = log2 N - 2, KS + starlet per map, as
+    one grouped graph-captured plan and as one launch sequence per map.
+    Inputs come from a pool of two generated maps per side (job i uses pool
+    entry i % 2); every job has its own output planes."""
+    import torch
+
+    import synth
+    import paper_1204_4293_amd as amap
+
+    dev = torch.device("cuda", 0)
+    sides = synth.uneven_batch_sides(512, 31)
+    pool = {}
+    for n in sorted(set(sides)):
+        pool[n] = []
+        for k in range(2):
+            _, g1, g2 = synth.shear_map(n, 1000 + 2 * n + k, 5000 + 2 * n + k)
+            pool[n].append((torch.tensor(g1, dtype=torch.float32, device=dev),
+                            torch.tensor(g2, dtype=torch.float32, device=dev)))
+    jobs = []
+    units = 0.0
+    b_alg = 0.0
+    for i, n in enumerate(sides):
+        J = n.bit_length() - 1 - 2
+        g1, g2 = pool[n][i % 2]
+        jobs.append({"g1": g1, "g2": g2,
+                     "planes": torch.empty((J, n, n), dtype=torch.float32, device=dev)})
+        units += n * n * J
+        b_alg += n * n * (8.0 + 4.0 * J)
+    plan = amap.BatchPlan(ctx, jobs)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run()  # captures the graph
+        plan.run()
+    side.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(side):
+        e0.record()
+        for _ in range(reps):
+            plan.run()
+        e1.record()
+    side.synchronize()
+    t_batched = e0.elapsed_time(e1) / reps * 1e-3
+
+    def plain_pass():
+        for j in jobs:
+            k, _ = ctx.ks_invert(j["g1"], j["g2"])
+            ctx.starlet_forward(k, j["planes"].shape[0], planes=j["planes"])
+
+    plain_pass()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(max(1, reps // 2)):
+        plain_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / max(1, reps // 2) * 1e-3
+    plan.close()
+    counts = {str(n): sides.count(n) for n in sorted(set(sides))}
+    return {"workload": "512 float32 maps, sides %s, J = log2 N - 2, KS + starlet" % counts,
+            "value": units / t_batched / 1e6, "unit": "Mpix·scales/s", "ms_per_batch": t_batched * 1e3,
+            "hbm_alg_GBps": b_alg / t_batched / 1e9,
+            "hbm_alg_frac": b_alg / t_batched / (HBM_PEAK_GBS * 1e9),
+            "bytes_alg": b_alg,
+            "plain": {"value": units / t_plain / 1e6, "ms_per_batch": t_plain * 1e3,
+                      "hbm_alg_frac": b_alg / t_plain / (HBM_PEAK_GBS * 1e9)}}
 
 
 def main():
@@ -140,7 +251,24 @@ def main():
     torch.cuda.synchronize()
     print("bench: warmup done", file=sys.stderr, flush=True)
 
-    # timed region: whole steps, wall clock and torch events on the launch stream
+    # per-kernel table: HIP events around every launch, over K untimed steps
+    ctx.timing_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ktimes = ctx.timing_read(reset=True)
+    B = min(R_REAL, max(1, (1 << 25) // (N * N)))
+    kernels = {}
+    for name, (launches, tot_ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
+        kernels[name] = {"launches_per_step": launches / args.steps,
+                         "avg_us": 1e3 * tot_ms / launches,
+                         "ms_per_step": tot_ms / args.steps}
+    dom = max(ktimes.items(), key=lambda kv: kv[1][1])[0]
+    starts = [int(k.rsplit("_j", 1)[1]) for k in ktimes if k.startswith("noise_stage_j")]
+
+    # timed region: K whole steps; only the dominant kernel carries HIP
+    # events (on its own launch stream), for its live average duration
+    ctx.timing_select(dom)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
@@ -153,34 +281,25 @@ def main():
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     units = 1 + R_REAL
     value = units * N * N * J / (ms_per_step * 1e-3) / 1e6
+    live = ctx.timing_read(reset=True)
+    ctx.timing_enable(False)
     print("bench: timed %d steps, %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr,
           flush=True)
 
-    # per-kernel HIP-event timing over the same number of steps
-    ctx.timing_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ktimes = ctx.timing_read(reset=True)
-    ctx.timing_enable(False)
-    B = min(R_REAL, max(1, (1 << 25) // (N * N)))
-    kernels = {}
-    for name, (launches, tot_ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
-        kernels[name] = {"launches_per_step": launches / args.steps,
-                         "avg_us": 1e3 * tot_ms / launches,
-                         "ms_per_step": tot_ms / args.steps}
-    dom = max(ktimes.items(), key=lambda kv: kv[1][1])[0]
-    dom_avg_s = ktimes[dom][1] / ktimes[dom][0] * 1e-3
-    b_alg, f_alg = kernel_model(dom, N, J, B)
+    dom_avg_s = live[dom][1] / live[dom][0] * 1e-3
+    b_alg, f_alg = kernel_model(dom, N, J, B, starts)
     for name, rec in kernels.items():
-        bb, ff = kernel_model(name, N, J, B)
+        bb, ff = kernel_model(name, N, J, B, starts)
         if bb is not None:
             rec["alg_GBps"] = bb / (rec["avg_us"] * 1e-6) / 1e9
             rec["alg_TFLOPs"] = ff / (rec["avg_us"] * 1e-6) / 1e12
+    traffic = measured_traffic(dom)
     roofline = {"kernel": dom, "bound": "hbm",
                 "achieved": b_alg / dom_avg_s / 1e9 if b_alg else None,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": traffic,
                 "bytes_per_launch": b_alg, "avg_launch_us": dom_avg_s * 1e6,
+                "launches_timed": live[dom][0],
                 "flops_per_launch": f_alg,
                 "tflops": f_alg / dom_avg_s / 1e12 if f_alg else None}
     roofline["frac"] = roofline["achieved"] / roofline["peak"] if b_alg else None
@@ -205,6 +324,9 @@ def main():
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
+    print("bench: uneven batch", file=sys.stderr, flush=True)
+    batched = uneven_batch(ctx, max(2, args.steps))
+
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix·scales/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -217,7 +339,7 @@ def main():
         "wall_s_timed": wall,
         "hbm_alg_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
                         / (HBM_PEAK_GBS * 1e9),
-        "plain": plain, "roofline": roofline, "kernels": kernels,
+        "plain": plain, "batched": batched, "roofline": roofline, "kernels": kernels,
     }
     ctx.close()
     if args.cpu_seconds > 0:

@@ -89,6 +89,12 @@ size_t amap_workspace_bytes(amap_ctx_t ctx);
  * Work captured into a batch plan's graph is not timed. */
 amap_status amap_timing_enable(amap_ctx_t ctx, int enable);
 
+/* Restricts the timing to launches of one kernel name (as reported by
+ * amap_timing_read); NULL or "" times every launch again.  Launches of
+ * other kernels then run without events around them.  AMAP_E_INVAL if
+ * timing is not enabled. */
+amap_status amap_timing_select(amap_ctx_t ctx, const char* kernel);
+
 /* Waits for the timed work and writes a JSON object
  * {"kernel": [launches, total_ms], ...} into buf (len bytes, including the
  * terminating NUL; AMAP_E_INVAL if it does not fit).  reset != 0 clears the
@@ -206,14 +212,20 @@ typedef struct {
     long long* peaks;   /* J-1 device counts when n_real>=2 */
 } amap_job;
 
-/* Validate `jobs` and build a plan that runs all of them.  The plan owns its
- * own workspace (independent of the context's) and a captured HIP graph per
- * stream; it keeps the job pointers until destroyed. */
+/* Validate `jobs` and build a plan that runs all of them.  Jobs without
+ * noise (n_real == 0) of one (n, J) are grouped: each group (in chunks of at
+ * most 2 GiB of workspace) runs as one launch per kernel over all its maps,
+ * which the kernels address through device tables of per-map pointers built
+ * here.  Jobs with noise run one after another.  The plan owns its workspace
+ * and tables (independent of the context's) and a captured HIP graph per
+ * stream; it keeps the job pointers until destroyed, and the caller keeps
+ * the buffers alive and unshared between jobs. */
 amap_status amap_batch_plan(amap_ctx_t ctx, amap_dtype dt, const amap_job* jobs,
                             int njobs, amap_plan_t* out);
 
 /* Run every job of the plan on `stream` (one graph launch after the first
- * call on that stream). */
+ * call on that stream).  On the null stream the kernels are launched
+ * directly, without a graph (and are timed when timing is enabled). */
 amap_status amap_batch_run(amap_plan_t plan, void* stream);
 
 /* Destroy a plan after waiting for its work; NULL is accepted. */

@@ -69,6 +69,7 @@ def load():
         "amap_workspace_bytes": (ctypes.c_size_t, [P]),
         "amap_timing_enable": (I, [P, I]),
         "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
+        "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
         "amap_starlet_forward": (I, [P, I, I, I, P, P, P]),
         "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
@@ -155,6 +156,10 @@ class Context:
     def timing_enable(self, enable=True):
         _check(load().amap_timing_enable(self._h, 1 if enable else 0))
 
+    def timing_select(self, kernel=None):
+        """Time only launches named ``kernel`` (None: all)."""
+        _check(load().amap_timing_select(self._h, kernel.encode() if kernel else None))
+
     def timing_read(self, reset=False):
         """{kernel: (launches, total_ms)} of the HIP-event timer."""
         import json
@@ -238,3 +243,56 @@ class Context:
                                     _ptr(o.get("kappa_b")), _ptr(o["planes"]), _ptr(o["sigma"]),
                                     _ptr(o["snr"]), _ptr(o["peaks"]), _stream()))
         return o
+
+
+class BatchPlan:
+    """A batch of maps run as one unit (amap_batch_plan / amap_batch_run).
+
+    ``jobs`` is a list of dicts with tensors ``g1``, ``g2``, ``planes`` and
+    optionally ``kappa_e``; jobs with noise realisations also carry
+    ``n_real``, ``seed``, ``threshold``, ``sigma``, ``snr`` and ``peaks``.
+    The plan keeps references to the tensors; on a non-default stream the
+    first run captures a graph that later runs replay.
+    """
+
+    def __init__(self, ctx, jobs):
+        if not jobs:
+            raise ValueError("need at least one job")
+        dt = _dt(jobs[0]["g1"])
+        arr = (AmapJob * len(jobs))()
+        self._keep = []
+        for i, j in enumerate(jobs):
+            n = _side(j["g1"])
+            if _dt(j["g1"]) != dt:
+                raise TypeError("all jobs of a plan share one dtype")
+            a = arr[i]
+            a.n = n
+            a.J = int(j["planes"].shape[0])
+            a.n_real = int(j.get("n_real", 0))
+            a.seed = int(j.get("seed", 0))
+            a.threshold = float(j.get("threshold", 3.0))
+            for key in ("g1", "g2", "kappa_e", "planes", "sigma", "snr", "peaks"):
+                t = j.get(key)
+                setattr(a, key, _ptr(t).value if t is not None else None)
+                if t is not None:
+                    self._keep.append(t)
+        self._jobs = arr
+        h = ctypes.c_void_p()
+        _check(load().amap_batch_plan(ctx._h, dt, arr, len(jobs), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+
+    def run(self):
+        _check(load().amap_batch_run(self._h, _stream()))
+
+    def close(self):
+        if self._h:
+            load().amap_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -48,6 +48,12 @@ struct KsArgs {
     uint64_t r0;
     const cpx<T>* tw;  // exp(-2 pi i k / 4096), k < 4096
     hipStream_t stream;
+    // grouped maps: device tables of per-map element offsets from g1, g2, kE
+    // (null: b * stride).  Offsets from a kernel-argument pointer keep the
+    // accesses in the global address space, so they stay vectorised.
+    const long long* g1_off = nullptr;
+    const long long* g2_off = nullptr;
+    const long long* kE_off = nullptr;
 };
 template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 
@@ -73,10 +79,18 @@ struct StarletArgs {
     double* M2;
     void* part;         // ACC: per-group partial statistics (starlet_partials_bytes)
     hipStream_t stream;
+    // grouped maps (write mode only): map m reads kappa + kappa_off[m] and
+    // writes its J planes at planes + planes_off[m] (element offsets); needs
+    // cbuf0 and cbuf1 and a tiled plan
+    const long long* kappa_off = nullptr;
+    const long long* planes_off = nullptr;
 };
 // Bytes of per-group partial statistics a noise batch may need.
 size_t starlet_partials_bytes(int logn, int batch);
 template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
+// True when every stage of an n x n, J-plane transform has an LDS tile
+// (grouped maps need it).
+template <typename T> bool starlet_all_tiled(int n, int J);
 template <typename T>
 hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStream_t s);
 

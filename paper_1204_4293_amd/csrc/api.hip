@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -112,6 +113,7 @@ struct EventTimer : KernelTimer {
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<long long, double>> totals;  // launches, ms
+    std::string only;  // time only launches of this name (empty: all)
 
     hipEvent_t get() {
         hipEvent_t e = nullptr;
@@ -124,6 +126,10 @@ struct EventTimer : KernelTimer {
         return e;
     }
     void begin(const char* name, hipStream_t s) override {
+        if (!only.empty() && only != name) {
+            pending.push_back(Rec{name, nullptr, nullptr});
+            return;
+        }
         Rec r{name, get(), get()};
         if (r.a) (void)hipEventRecord(r.a, s);
         pending.push_back(r);
@@ -412,6 +418,16 @@ amap_status amap_timing_enable(amap_ctx_t c, int enable) {
         delete c->timer;
         c->timer = nullptr;
     }
+    return AMAP_OK;
+}
+
+amap_status amap_timing_select(amap_ctx_t c, const char* kernel) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!c->timer) return fail(AMAP_E_INVAL, "timing is not enabled");
+    DeviceGuard g(c->device);
+    c->timer->flush();
+    c->timer->only = kernel ? kernel : "";
     return AMAP_OK;
 }
 
@@ -761,10 +777,23 @@ size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real) {
 
 }  // extern "C"
 
+// A batch plan.  Jobs without noise realisations whose size has an LDS tile
+// for every starlet stage are grouped by (n, J) into chunks; one chunk runs
+// as one launch per kernel, the maps addressed through device tables of
+// per-map pointers.  Other jobs (noise, untiled sizes) run one after another.
+struct PlanChunk {
+    int n, J, count;
+    size_t tab_off;              // byte offset of the chunk's tables in amap_plan::tabs
+    char* base[4];               // g1, g2, kappa, planes of the chunk's first map
+};
+
 struct amap_plan {
     amap_ctx* ctx = nullptr;
     amap_dtype dt = AMAP_F32;
     std::vector<amap_job> jobs;
+    std::vector<PlanChunk> chunks;
+    std::vector<int> singles;    // indices of jobs run one at a time
+    void* tabs = nullptr;        // device: per chunk [g1 | g2 | kappa | planes] x count offsets
     Workspace ws;
     hipStream_t graph_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -778,11 +807,52 @@ struct amap_plan {
     }
 };
 
-static amap_status enqueue_plan(amap_plan* p, hipStream_t s) {
+// Device bytes a chunk of `count` maps needs: spectra, kappa slots and the two
+// c buffers of the starlet stages.
+static size_t chunk_workspace_bytes(amap_dtype dt, int n, int count) {
+    const size_t plane = (size_t)n * n * esize(dt);
+    return align256(2 * plane * count) + 3 * align256(plane * count);
+}
+
+constexpr size_t kChunkBytes = 2ull << 30;  // workspace of one grouped chunk, at most
+
+template <typename T>
+static amap_status enqueue_chunk(const amap_plan* p, const PlanChunk& ch, hipStream_t s) {
+    const size_t plane = (size_t)ch.n * ch.n * sizeof(T);
+    const int logn = ilog2(ch.n);
+    const long long n2 = (long long)ch.n * ch.n;
     char* w = static_cast<char*>(p->ws.ptr);
-    for (const amap_job& j : p->jobs)
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(w);
+    T* cb0 = reinterpret_cast<T*>(w + align256(2 * plane * ch.count) + align256(plane * ch.count));
+    T* cb1 = reinterpret_cast<T*>(reinterpret_cast<char*>(cb0) + align256(plane * ch.count));
+    // tables: [g1 | g2 | kappa | planes] x count element offsets from the
+    // chunk's base pointers
+    const long long* off = reinterpret_cast<const long long*>(static_cast<char*>(p->tabs) + ch.tab_off);
+    KsArgs<T> k;
+    k.logn = logn; k.batch = ch.count; k.g1 = (const T*)ch.base[0]; k.g2 = (const T*)ch.base[1];
+    k.g_stride = 0; k.C = C; k.kE = (T*)ch.base[2]; k.kB = nullptr; k.out_stride = n2;
+    k.rotate = false; k.seed = 0; k.r0 = 0; k.tw = twiddles<T>(p->ctx); k.stream = s;
+    k.g1_off = off; k.g2_off = off + ch.count; k.kE_off = off + 2 * ch.count;
+    AMAP_HIP(launch_ks<T>(k), "KS kernels (grouped)");
+    StarletArgs<T> a;
+    a.logn = logn; a.J = ch.J; a.batch = ch.count; a.done = 0; a.kappa = (const T*)ch.base[2];
+    a.in_stride = n2; a.planes = (T*)ch.base[3]; a.planes_stride = 0; a.cbuf0 = cb0; a.cbuf1 = cb1;
+    a.tmp = nullptr; a.wbuf = nullptr; a.M = nullptr; a.M2 = nullptr; a.part = nullptr; a.stream = s;
+    a.kappa_off = off + 2 * ch.count;
+    a.planes_off = off + 3 * ch.count;
+    AMAP_HIP(launch_starlet<T>(a), "starlet kernels (grouped)");
+    return AMAP_OK;
+}
+
+static amap_status enqueue_plan(amap_plan* p, hipStream_t s) {
+    for (const PlanChunk& ch : p->chunks)
+        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_chunk<float>(p, ch, s) : enqueue_chunk<double>(p, ch, s));
+    char* w = static_cast<char*>(p->ws.ptr);
+    for (int i : p->singles) {
+        const amap_job& j = p->jobs[i];
         AMAP_TRY(p->dt == AMAP_F32 ? enqueue_job<float>(p->ctx, w, j, s)
                                    : enqueue_job<double>(p->ctx, w, j, s));
+    }
     return AMAP_OK;
 }
 
@@ -795,7 +865,6 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
     if (!out) return fail(AMAP_E_INVAL, "out must not be NULL");
     *out = nullptr;
     if (njobs < 1 || !jobs) return fail(AMAP_E_INVAL, "need at least one job");
-    size_t need = 0;
     for (int i = 0; i < njobs; ++i) {
         amap_status st = validate_job(dt, jobs[i]);
         if (st != AMAP_OK) {
@@ -804,8 +873,6 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
         }
         if (jobs[i].n_real == 1 || jobs[i].n_real < 0)
             return fail(AMAP_E_INVAL, "job %d: n_real must be 0 or >= 2", i);
-        const size_t b = job_workspace_bytes(dt, jobs[i]);
-        need = b > need ? b : need;
     }
     DeviceGuard g(c->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
@@ -815,8 +882,64 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
     p->ctx = c;
     p->dt = dt;
     p->jobs.assign(jobs, jobs + njobs);
+    // group: (n, J) -> job indices, in job order
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < njobs; ++i) {
+        const amap_job& j = jobs[i];
+        const bool tiled = dt == AMAP_F32 ? starlet_all_tiled<float>(j.n, j.J)
+                                          : starlet_all_tiled<double>(j.n, j.J);
+        if (j.n_real == 0 && tiled) groups[{j.n, j.J}].push_back(i);
+        else p->singles.push_back(i);
+    }
+    size_t need = 0, tab_bytes = 0;
+    for (int i : p->singles) need = std::max(need, job_workspace_bytes(dt, jobs[i]));
+    for (auto& kv : groups) {
+        const int n = kv.first.first, J = kv.first.second;
+        const size_t per = chunk_workspace_bytes(dt, n, 1);
+        const int cap = (int)std::max<size_t>(1, kChunkBytes / per);
+        const std::vector<int>& idx = kv.second;
+        for (size_t k = 0; k < idx.size(); k += cap) {
+            const int cnt = (int)std::min<size_t>(cap, idx.size() - k);
+            p->chunks.push_back(PlanChunk{n, J, cnt, tab_bytes, {nullptr, nullptr, nullptr, nullptr}});
+            tab_bytes += align256(4 * sizeof(long long) * cnt);
+            need = std::max(need, chunk_workspace_bytes(dt, n, cnt));
+        }
+    }
     amap_status st = p->ws.reserve(need);
+    if (st == AMAP_OK && tab_bytes) {
+        std::vector<long long> host(tab_bytes / sizeof(long long), 0);
+        char* ws = static_cast<char*>(p->ws.ptr);
+        const size_t es = esize(dt);
+        size_t ci = 0;
+        for (auto& kv : groups) {
+            const int n = kv.first.first;
+            const size_t plane = (size_t)n * n * es;
+            const std::vector<int>& idx = kv.second;
+            for (size_t k = 0; k < idx.size();) {
+                PlanChunk& ch = p->chunks[ci++];
+                long long* t = host.data() + ch.tab_off / sizeof(long long);
+                char* kslot = ws + align256(2 * plane * ch.count);
+                for (int m = 0; m < ch.count; ++m, ++k) {
+                    const amap_job& j = jobs[idx[k]];
+                    char* ptr[4] = {(char*)j.g1, (char*)j.g2,
+                                    j.kappa_e ? (char*)j.kappa_e : kslot + plane * m, (char*)j.planes};
+                    for (int q = 0; q < 4; ++q) {
+                        if (m == 0) ch.base[q] = ptr[q];
+                        // element offset from the chunk's base (buffers are 256-byte aligned)
+                        t[q * ch.count + m] = (long long)((intptr_t)ptr[q] - (intptr_t)ch.base[q]) / (long long)es;
+                    }
+                }
+            }
+        }
+        if (hipMalloc(&p->tabs, tab_bytes) != hipSuccess) {
+            st = fail(AMAP_E_NOMEM, "cannot allocate %zu bytes of map tables", tab_bytes);
+        } else if (hipMemcpy(p->tabs, host.data(), tab_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            st = fail(AMAP_E_HIP, "cannot upload map tables");
+        }
+    }
     if (st != AMAP_OK) {
+        if (p->tabs) (void)hipFree(p->tabs);
+        p->ws.release();
         delete p;
         return st;
     }
@@ -830,7 +953,10 @@ amap_status amap_batch_run(amap_plan_t p, void* stream) {
     DeviceGuard g(p->ctx->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", p->ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!s) return enqueue_plan(p, s);  // the null stream cannot be captured
+    if (!s) {  // the null stream cannot be captured: launch directly (timed if enabled)
+        TimerScope ts(p->ctx);
+        return enqueue_plan(p, s);
+    }
     if (!p->exec || p->graph_stream != s) {
         p->drop_graph();
         AMAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -860,6 +986,7 @@ amap_status amap_plan_destroy(amap_plan_t p) {
     DeviceGuard g(p->ctx->device);
     (void)hipDeviceSynchronize();
     p->drop_graph();
+    if (p->tabs) (void)hipFree(p->tabs);
     p->ws.release();
     delete p;
     return AMAP_OK;

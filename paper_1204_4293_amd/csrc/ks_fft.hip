@@ -158,6 +158,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 template <typename T, int LOGN, bool ROTATE>
 __global__ void __launch_bounds__((StripCfg<T, LOGN>::NT))
 k_ks_cols_fwd_generic(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
+              const long long* __restrict__ g1_off, const long long* __restrict__ g2_off,
               cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0,
               const cpx<T>* __restrict__ tw) {
     using Cfg = StripCfg<T, LOGN>;
@@ -165,8 +166,8 @@ k_ks_cols_fwd_generic(const T* __restrict__ g1, const T* __restrict__ g2, long l
     __shared__ cpx<T> buf[N * W];
     const int b = blockIdx.y;
     const int x0 = blockIdx.x * W;
-    const T* a1 = g1 + (long long)b * g_stride;
-    const T* a2 = g2 + (long long)b * g_stride;
+    const T* a1 = g1 + (g1_off ? g1_off[b] : (long long)b * g_stride);
+    const T* a2 = g2 + (g2_off ? g2_off[b] : (long long)b * g_stride);
     if (ROTATE) {
         // one Philox block covers 8 consecutive pixels of a row
         constexpr int OCT_PER_ROW = (W + 7) / 8;
@@ -242,7 +243,7 @@ k_ks_rows_generic(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((StripCfg<T, LOGN>::NT))
 k_ks_cols_inv_generic(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
-              long long out_stride, const cpx<T>* __restrict__ tw) {
+              long long out_stride, const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw) {
     using Cfg = StripCfg<T, LOGN>;
     constexpr int N = Cfg::N, W = Cfg::W, NT = Cfg::NT;
     __shared__ cpx<T> buf[N * W];
@@ -255,7 +256,7 @@ k_ks_cols_inv_generic(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __res
     }
     __syncthreads();
     lds_fft<T, LOGN, W, NT, W, 1, true, true>(buf, tw);
-    T* oe = kE + (long long)b * out_stride;
+    T* oe = kE + (kE_off ? kE_off[b] : (long long)b * out_stride);
     T* ob = kB ? kB + (long long)b * out_stride : nullptr;
     for (int e = threadIdx.x; e < N * W; e += NT) {
         const int y = e / W, c = e % W;
@@ -331,6 +332,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <typename T, int LOGN, bool ROTATE>
 __global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
 k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
+              const long long* __restrict__ g1_off, const long long* __restrict__ g2_off,
               cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0, const cpx<T>* __restrict__ tw) {
     using F = FS<LOGN>;
     using S = Strip4<T, LOGN>;
@@ -338,8 +340,8 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
     __shared__ cpx<T> buf[N * W];
     const int b = blockIdx.y;
     const int x0 = blockIdx.x * W;
-    const T* a1 = g1 + (long long)b * g_stride;
-    const T* a2 = g2 + (long long)b * g_stride;
+    const T* a1 = g1 + (g1_off ? g1_off[b] : (long long)b * g_stride);
+    const T* a2 = g2 + (g2_off ? g2_off[b] : (long long)b * g_stride);
     if (ROTATE) {
         // one Philox block covers 8 consecutive pixels of a row
         constexpr int OCT_PER_ROW = (W + 7) / 8;
@@ -464,7 +466,7 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
 k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
-              long long out_stride, const cpx<T>* __restrict__ tw) {
+              long long out_stride, const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw) {
     using F = FS<LOGN>;
     using S = Strip4<T, LOGN>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W;
@@ -482,7 +484,7 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
         buf[(k1 * N2 + t) * W + c] = cmul(a[k1], w);
     });
     __syncthreads();
-    T* oe = kE + (long long)b * out_stride + x0 + c;
+    T* oe = kE + (kE_off ? kE_off[b] : (long long)b * out_stride) + x0 + c;
     T* ob = kB ? kB + (long long)b * out_stride + x0 + c : nullptr;
 #pragma unroll
     for (int r = 0; r < F::RR; ++r) {
@@ -501,10 +503,11 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
 }
 
 // ---- host launchers ------------------------------------------------------------
-// Transforms whose per-thread DFTs would spill registers (float32 from 2048,
-// float64 from 1024) keep their data in LDS.
+// Double-precision transforms from 1024 points keep their data in LDS (their
+// per-thread DFTs would not fit the register file); everything else runs the
+// four-step register kernels.
 template <typename T, int LOGN>
-constexpr bool use_generic() { return sizeof(T) == 8 ? LOGN >= 10 : LOGN >= 11; }
+constexpr bool use_generic() { return sizeof(T) == 8 && LOGN >= 10; }
 
 template <typename T, int LOGN>
 static hipError_t ks_launch_n(const KsArgs<T>& a) {
@@ -516,16 +519,16 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
         if (a.rotate)
             AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
                         k_ks_cols_fwd_generic<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
         else
             AMAP_LAUNCH("ks_cols_fwd", a.stream,
                         k_ks_cols_fwd_generic<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
         AMAP_LAUNCH("ks_rows", a.stream,
                     k_ks_rows_generic<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
         AMAP_LAUNCH("ks_cols_inv", a.stream,
                     k_ks_cols_inv_generic<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
-                                                                                a.out_stride, a.tw));
+                                                                                a.out_stride, a.kE_off, a.tw));
     } else {
         using S = Strip4<T, LOGN>;
         using R = Row4<T, LOGN>;
@@ -533,15 +536,15 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
         if (a.rotate)
             AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
                         k_ks_cols_fwd<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
         else
             AMAP_LAUNCH("ks_cols_fwd", a.stream,
                         k_ks_cols_fwd<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.C, a.seed, a.r0, a.tw));
+                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
         AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
         AMAP_LAUNCH("ks_cols_inv", a.stream,
                     k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
-                                                                        a.out_stride, a.tw));
+                                                                        a.out_stride, a.kE_off, a.tw));
     }
     return hipGetLastError();
 }

@@ -49,6 +49,13 @@ struct StageArgs {
     int plane_base;
     T* cout;                     // c_{j0+ns-1}, or null
     long long cout_stride;
+    // grouped maps (null: the strided addressing above): map m reads
+    // src + src_off[m] and writes its planes at planes + planes_off[m]
+    // (element offsets); cout_plane >= 0 puts c_{j0+ns-1} in that plane of
+    // the map's planes instead of cout
+    const long long* src_off = nullptr;
+    const long long* planes_off = nullptr;
+    int cout_plane = -1;
 };
 
 // 16-byte vectors: four floats or two doubles
@@ -298,7 +305,7 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
     T* A = reinterpret_cast<T*>(smem_raw) + G;  // element (v, i) at A[v*RS + i], i in [-G, TXT+G)
     T* Bf = A + g.RS * g.TVT;
     const int map = blockIdx.y;
-    const T* src = a.src + (long long)map * a.src_stride;
+    const T* src = a.src + (a.src_off ? a.src_off[map] : (long long)map * a.src_stride);
     const int tvec = g.TXT / G;
     for (int v = wave; v < g.TVT; v += NW) {
         const long long row = tile_row(g, v);
@@ -308,7 +315,7 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
     lds_barrier();
     VA prev[kVecPerThread];
     load_owned<T, NT, kVecPerThread>(A, g, prev);
-    T* planes = a.planes + (long long)map * a.planes_stride;
+    T* planes = a.planes + (a.planes_off ? a.planes_off[map] : (long long)map * a.planes_stride);
     int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
     for (int s = 0; s < a.ns; ++s) {
         tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
@@ -327,7 +334,10 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
             }
         }
     }
-    if (a.cout) store_owned<T, NT, kVecPerThread>(a.cout + (long long)map * a.cout_stride, g, prev);
+    if (a.cout_plane >= 0)
+        store_owned<T, NT, kVecPerThread>(planes + (long long)a.cout_plane * n2, g, prev);
+    else if (a.cout)
+        store_owned<T, NT, kVecPerThread>(a.cout + (long long)map * a.cout_stride, g, prev);
 }
 
 // Noise mode: each workgroup owns one tile and takes the realisations
@@ -349,13 +359,13 @@ struct NoiseStageArgs {
     float inv_tvec;          // 1 / (vectors per tile row), for index splitting
 };
 
-template <typename T, int NT>
+template <typename T, int NT, int NS>
 __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
     using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
-    const TileGeom g = tile_geom(a.logn, a.j0, a.ns, a.log_tw, a.th, G);
+    const TileGeom g = tile_geom(a.logn, a.j0, NS, a.log_tw, a.th, G);
     const long long n2 = (long long)g.n * g.n;
     T* A = reinterpret_cast<T*>(smem_raw) + G;
     T* Bf = A + g.RS * g.TVT;
@@ -366,9 +376,9 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
 
     constexpr int PF = noise_prefetch(NT);
     VA pf[PF];
-    AccT mean[3][G], m2[3][G];
+    AccT mean[NS][G], m2[NS][G];
 #pragma unroll
-    for (int s = 0; s < 3; ++s)
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int c = 0; c < G; ++c) mean[s][c] = m2[s][c] = (AccT)0;
     const bool owner = (int)threadIdx.x < g.nvec;
@@ -414,8 +424,7 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
         const AccT inv = (AccT)1 / (AccT)(it + 1);
         int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {  // unrolled: the Welford state keeps static indices
-            if (s >= a.ns) break;
+        for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
             tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
             if (owner) {
                 const VA c = vload<T, G>(A + owned_lds(g, own_e));
@@ -435,8 +444,7 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
     if (!owner) return;
     const long long base = owned_global(g, own_e);
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        if (s >= a.ns) break;
+    for (int s = 0; s < NS; ++s) {
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             const long long gi = (long long)s * n2 + base + c;
@@ -446,7 +454,7 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
                 a.M[gi] += delta * (nb / nt);
                 a.M2[gi] += (double)m2[s][c] + delta * delta * (na * nb / nt);
             } else {
-                AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * a.ns + s) * 2 * n2;
+                AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
                 pp[base + c] = mean[s][c];
                 pp[n2 + base + c] = m2[s][c];
             }
@@ -569,7 +577,7 @@ constexpr double kMaxHaloRatio = 2.6;
 // in LDS and whose halo overhead is bounded; among those, the smallest
 // overhead.  Returns false if no tile exists even for one scale.
 template <typename T>
-static bool pick_stage(int n, int j0, int left, StageGeom* g) {
+static bool pick_stage(int n, int j0, int left, bool noise, StageGeom* g) {
     constexpr int G = Vec<T>::G;
     const int d0 = 1 << (j0 - 1);
     for (int ns = left < 3 ? left : 3; ns >= 1; --ns) {
@@ -588,8 +596,10 @@ static bool pick_stage(int n, int j0, int left, StageGeom* g) {
                 int nt = tw * th / (G * kVecPerThread);
                 nt = nt < 256 ? 256 : (nt > 512 ? 512 : nt);
                 if (tw * th > nt * G * kVecPerThread) continue;
-                if ((TXT / G) * TVT > nt * kPrefetch) continue;  // noise-mode prefetch
-                if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per noise thread
+                if (noise) {
+                    if ((TXT / G) * TVT > nt * kPrefetch) continue;  // prefetch registers
+                    if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per thread
+                }
                 // prefer small overhead, then more workgroups per CU (less LDS)
                 if (!found || ratio < best_ratio - 1e-9 ||
                     (ratio < best_ratio + 1e-9 && lds < best.lds)) {
@@ -638,12 +648,12 @@ static hipError_t launch_stage(const StageArgs<T>& a, const StageGeom& g, int ma
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int NS>
 static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
                                         hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -660,7 +670,7 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                     "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
                                     "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
     AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
-                k_starlet_noise_stage<T, NT><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+                k_starlet_noise_stage<T, NT, NS><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
     return hipGetLastError();
 }
 
@@ -671,13 +681,26 @@ static int noise_threads(const StageGeom& g, int G) {
     return nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
 }
 
+template <typename T, int NS>
+static hipError_t launch_noise_stage_ns(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
+                                        hipStream_t s) {
+    switch (noise_threads(g, Vec<T>::G)) {
+        case 256: return launch_noise_stage_nt<T, 256, NS>(a, g, tiles, s);
+        case 512: return launch_noise_stage_nt<T, 512, NS>(a, g, tiles, s);
+        case 1024:  // double-precision tiles hold at most 512 vectors
+            if constexpr (sizeof(T) == 4) return launch_noise_stage_nt<T, 1024, NS>(a, g, tiles, s);
+            return hipErrorInvalidConfiguration;
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 static hipError_t launch_noise_stage(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
                                      hipStream_t s) {
-    switch (noise_threads(g, Vec<T>::G)) {
-        case 256: return launch_noise_stage_nt<T, 256>(a, g, tiles, s);
-        case 512: return launch_noise_stage_nt<T, 512>(a, g, tiles, s);
-        case 1024: return launch_noise_stage_nt<T, 1024>(a, g, tiles, s);
+    switch (a.ns) {
+        case 1: return launch_noise_stage_ns<T, 1>(a, g, tiles, s);
+        case 2: return launch_noise_stage_ns<T, 2>(a, g, tiles, s);
+        case 3: return launch_noise_stage_ns<T, 3>(a, g, tiles, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -721,6 +744,18 @@ static hipError_t per_scale_stage(int logn, int j0, int ns, int maps, const T* c
 // Noise batches write each stage's planes into wbuf ([batch][3][n^2]) and
 // merge them into (M, M2) before the next stage.
 template <typename T>
+bool starlet_all_tiled(int n, int J) {
+    for (int j0 = 1; j0 < J;) {
+        StageGeom g{};
+        if (!pick_stage<T>(n, j0, J - j0, false, &g)) return false;
+        j0 += g.ns;
+    }
+    return true;
+}
+template bool starlet_all_tiled<float>(int, int);
+template bool starlet_all_tiled<double>(int, int);
+
+template <typename T>
 hipError_t launch_starlet(const StarletArgs<T>& a) {
     const int n = 1 << a.logn;
     const long long n2 = (long long)n * n;
@@ -731,10 +766,33 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     int nstages = 0;
     for (int j0 = 1; j0 < a.J; ) {
         StageGeom g{};
-        const bool tiled = pick_stage<T>(n, j0, a.J - j0, &g);
+        const bool tiled = pick_stage<T>(n, j0, a.J - j0, acc, &g);
         const int ns = tiled ? g.ns : 1;
         plan[nstages++] = Stage{j0, ns, g, tiled};
         j0 += ns;
+    }
+    if (a.planes_off) {
+        // grouped maps: c ping-pongs between cbuf0 and cbuf1; the last stage
+        // writes c_{J-1} into each map's last plane
+        if (acc || !a.kappa_off || !a.cbuf0 || !a.cbuf1) return hipErrorInvalidValue;
+        const T* cur = nullptr;
+        for (int gi = 0; gi < nstages; ++gi) {
+            const Stage& st = plan[gi];
+            if (!st.tiled) return hipErrorNotSupported;
+            const bool last = gi == nstages - 1;
+            int lt = 0;
+            while ((1 << lt) < st.g.tw) ++lt;
+            StageArgs<T> s;
+            s.logn = a.logn; s.j0 = st.j0; s.ns = st.ns; s.log_tw = lt; s.th = st.g.th;
+            s.src = gi == 0 ? a.kappa : cur; s.src_stride = n2; s.src_off = gi == 0 ? a.kappa_off : nullptr;
+            s.planes = a.planes; s.planes_stride = 0; s.planes_off = a.planes_off; s.plane_base = 0;
+            T* dst = last ? nullptr : (cur == a.cbuf0 ? a.cbuf1 : a.cbuf0);
+            s.cout = dst; s.cout_stride = n2; s.cout_plane = last ? a.J - 1 : -1;
+            const hipError_t e = launch_stage<T>(s, st.g, a.batch, a.stream);
+            if (e != hipSuccess) return e;
+            cur = dst;
+        }
+        return hipGetLastError();
     }
     T* final_c = acc ? nullptr : a.planes + (long long)(a.J - 1) * n2;
     const long long final_stride = a.planes_stride;

@@ -1,0 +1,165 @@
+"""Batch plans (grouped maps of uneven sizes, graph-captured) against the
+single-map calls and the FP64 oracle.
+
+Grouped maps run the same kernels as single maps, so their outputs are
+compared bit for bit with the single-map path; sampled maps are also
+checked against the oracle at 1e-5 * rms(kappa) (float32) or 1e-10
+(float64), and every map of the uneven batch against the reconstruction
+identity kappa = c_{J-1} + sum_j w_j, which holds at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth as S
+import paper_1204_4293_amd as amap
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-5, torch.float64: 1e-10}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = amap.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def rms(a):
+    return float(np.sqrt(np.mean(np.asarray(a, dtype=np.float64) ** 2)))
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))))
+
+
+def make_jobs(sides, dtype, seed0, want_kappa):
+    jobs, refs = [], []
+    for i, n in enumerate(sides):
+        J = max(2, n.bit_length() - 1 - 2)
+        _, g1, g2 = S.shear_map(n, seed0 + i, seed0 + 500 + i)
+        job = {"g1": dev(g1, dtype), "g2": dev(g2, dtype),
+               "planes": torch.full((J, n, n), float("nan"), dtype=dtype, device="cuda")}
+        if want_kappa(i):
+            job["kappa_e"] = torch.full((n, n), float("nan"), dtype=dtype, device="cuda")
+        jobs.append(job)
+        refs.append((g1, g2, J))
+    return jobs, refs
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_grouped_plan_replays_match_single_maps_and_oracle(ctx, dtype):
+    sides = [64, 128, 64, 256, 128, 64, 32, 256]
+    print("grouped plan %s sides=%s" % (dtype, sides), flush=True)
+    jobs, refs = make_jobs(sides, dtype, 200, lambda i: i % 3 == 0)
+    plan = amap.BatchPlan(ctx, jobs)
+    side = torch.cuda.Stream()
+    single = []
+    for (g1, g2, J), job in zip(refs, jobs):
+        k, _ = ctx.ks_invert(job["g1"], job["g2"])
+        single.append((k, ctx.starlet_forward(k, J)))
+    torch.cuda.synchronize()
+    first = None
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            plan.run()       # the first run captures the graph, later runs replay it
+        side.synchronize()
+        # eager work of the program between replays
+        ctx.ks_invert(jobs[0]["g1"], jobs[0]["g2"])
+        torch.cuda.synchronize()
+        outs = [j["planes"].clone() for j in jobs]
+        if first is None:
+            first = outs
+        for i, (job, (k1, p1)) in enumerate(zip(jobs, single)):
+            assert torch.equal(outs[i], first[i]), "replay %d map %d differs" % (rep, i)
+            assert torch.equal(outs[i], p1), "map %d differs from the single-map path" % i
+            if "kappa_e" in job:
+                assert torch.equal(job["kappa_e"], k1)
+        for j in jobs:
+            j["planes"].fill_(float("nan"))
+    # oracle on every map (small sizes)
+    with torch.cuda.stream(side):
+        plan.run()
+    side.synchronize()
+    for (g1, g2, J), job in zip(refs, jobs):
+        kE, _ = O.ks_invert(g1, g2)
+        ref = O.starlet_forward(kE, J)
+        assert maxerr(host(job["planes"]), ref) <= TOL[dtype] * rms(kE)
+    plan.close()
+
+
+def test_plan_with_noise_job_matches_run_path(ctx):
+    n, J, R, seed = 64, 4, 6, 77
+    jobs, refs = make_jobs([64, 64, 128], torch.float32, 300, lambda i: False)
+    _, g1, g2 = S.shear_map(n, 310, 311)
+    t1, t2 = dev(g1, torch.float32), dev(g2, torch.float32)
+    noise_job = {"g1": t1, "g2": t2, "n_real": R, "seed": seed, "threshold": 2.0,
+                 "planes": torch.empty((J, n, n), device="cuda"),
+                 "sigma": torch.empty((J - 1, n, n), device="cuda"),
+                 "snr": torch.empty((J - 1, n, n), device="cuda"),
+                 "peaks": torch.zeros(J - 1, dtype=torch.int64, device="cuda")}
+    plan = amap.BatchPlan(ctx, jobs + [noise_job])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run()
+    side.synchronize()
+    ref = ctx.run_path(t1, t2, J, R, seed, 2.0)
+    torch.cuda.synchronize()
+    for key in ("planes", "sigma", "snr", "peaks"):
+        assert torch.equal(noise_job[key], ref[key]), key
+    for (g1, g2, J), job in zip(refs, jobs):
+        kE, _ = O.ks_invert(g1, g2)
+        assert maxerr(host(job["planes"]), O.starlet_forward(kE, J)) <= 1e-5 * rms(kE)
+    plan.close()
+
+
+def test_uneven_batch_sampled_against_oracle(ctx):
+    # the uneven-batch size distribution (sides 128..2048, weights 4:4:3:2:1),
+    # first 40 draws; per-map seeds 1000 + i; J = log2 N - 2
+    sides = S.uneven_batch_sides(40, 31)
+    assert 2048 in sides and 128 in sides
+    print("uneven batch sides=%s" % sides, flush=True)
+    jobs, refs = make_jobs(sides, torch.float32, 1000, lambda i: True)
+    plan = amap.BatchPlan(ctx, jobs)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run()
+    side.synchronize()
+    # every map: exact reconstruction and zero-mean detail planes
+    for job in jobs:
+        p = job["planes"].double()
+        k = job["kappa_e"].double()
+        r = float(k.pow(2).mean().sqrt())
+        assert float((p.sum(0) - k).abs().max()) <= 1e-5 * r
+        assert float(p[:-1].mean(dim=(1, 2)).abs().max()) <= 1e-6 * r
+    # sampled maps: the first of each size against the oracle
+    seen = set()
+    for (g1, g2, J), job, n in zip(refs, jobs, sides):
+        if n in seen:
+            continue
+        seen.add(n)
+        kE, _ = O.ks_invert(g1, g2)
+        tol = 1e-5 * rms(kE)
+        assert maxerr(host(job["kappa_e"]), kE) <= tol
+        assert maxerr(host(job["planes"]), O.starlet_forward(kE, J)) <= tol
+    plan.close()
+
+
+def test_plan_rejects_bad_jobs(ctx):
+    g = torch.zeros((64, 64), device="cuda")
+    with pytest.raises(amap.AmapError):
+        amap.BatchPlan(ctx, [{"g1": g, "g2": g, "planes": torch.empty((7, 64, 64), device="cuda")}])
+    with pytest.raises(amap.AmapError):
+        amap.BatchPlan(ctx, [{"g1": g, "g2": g, "n_real": 1,
+                              "planes": torch.empty((3, 64, 64), device="cuda")}])
