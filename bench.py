@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle's timed sample (0 to skip)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the uneven-batch measurement (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -324,8 +326,10 @@ def main():
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
-    print("bench: uneven batch", file=sys.stderr, flush=True)
-    batched = uneven_batch(ctx, max(2, args.steps))
+    batched = None
+    if not args.no_batched:
+        print("bench: uneven batch", file=sys.stderr, flush=True)
+        batched = uneven_batch(ctx, max(2, args.steps))
 
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix·scales/s", "n_gpus": 1,
