@@ -13,6 +13,8 @@ Printed as one JSON line.  Extra objects:
   plain        one map through KS + starlet, one launch sequence per map
   batched      512 uneven maps (KS + starlet) as one grouped, graph-captured
                plan, and the same maps one launch sequence per map
+  served       a Poisson request stream through the library's request loop:
+               saturated rate, then p50/p99 latency at 0.5 and 0.8 of it
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -75,13 +77,13 @@ def kernel_model(name, n, J, batch_real, stage_starts=()):
 
 
 def kernel_sources_sha256():
-    """Digest of the library's kernel sources; a stored counter summary is
-    only used while it matches."""
+    """Digest of the library's kernel sources (every source but the host-only
+    api.hip); a stored counter summary is only used while it matches."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1204_4293_amd", "csrc")
     for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h")) and f != "api.hip":  # api.hip is host code only
             with open(os.path.join(src, f), "rb") as fh:
                 h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -202,6 +204,90 @@ def uneven_batch(ctx, reps):
                       "hbm_alg_frac": b_alg / t_plain / (HBM_PEAK_GBS * 1e9)}}
 
 
+def served_stream(ctx, level_seconds):
+    """The served stream: Poisson arrivals of float32 maps with sides
+    log-uniform over 256..4096 (seeds 41, 42), J = min(9, log2 N - 2), 32 noise
+    realisations each, through the library's request loop (footprint
+    admission, 8 concurrent slots).  Inputs come from a device-resident pool
+    of two maps per side; outputs come from a fixed set of buffers per side
+    (requests wait for one on the client side, inside their latency).  First a burst
+    gives the saturated request rate mu, then the stream runs at 0.5 mu and
+    0.8 mu; latency is arrival -> completion seen by polling."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1204_4293_amd as amap
+
+    dev = torch.device("cuda", 0)
+    R = 32
+    pool = {}
+    for n in (256, 512, 1024, 2048, 4096):
+        pool[n] = []
+        for k in range(2):
+            _, g1, g2 = synth.shear_map(n, 7000 + 2 * n + k, 9000 + 2 * n + k)
+            pool[n].append((torch.tensor(g1, dtype=torch.float32, device=dev),
+                            torch.tensor(g2, dtype=torch.float32, device=dev)))
+    srv = amap.Server(ctx, torch.float32, mem_budget=48 << 30, max_inflight=8, max_queued=100000)
+    # output buffers: a fixed set per side, reused; a request waits on the
+    # client side (inside its latency) until a set of its side is free
+    depth = {256: 16, 512: 16, 1024: 12, 2048: 8, 4096: 6}
+    free = {}
+    for n, dpt in depth.items():
+        J = min(9, n.bit_length() - 1 - 2)
+        free[n] = [{"planes": torch.empty((J, n, n), device=dev),
+                    "sigma": torch.empty((J - 1, n, n), device=dev),
+                    "snr": torch.empty((J - 1, n, n), device=dev),
+                    "peaks": torch.empty(J - 1, dtype=torch.int64, device=dev)} for _ in range(dpt)]
+
+    def run(times, sides):
+        t0 = time.perf_counter()
+        pending, lat, units, i, done_at = {}, [], 0.0, 0, t0
+        backlog = []
+        while i < len(times) or backlog or pending:
+            now = time.perf_counter()
+            while i < len(times) and t0 + times[i] <= now:
+                backlog.append(i)
+                i += 1
+            while backlog and free[sides[backlog[0]]]:
+                k = backlog.pop(0)
+                n = sides[k]
+                J = min(9, n.bit_length() - 1 - 2)
+                outs = free[n].pop()
+                g1, g2 = pool[n][k % 2]
+                job = dict(outs, g1=g1, g2=g2, n_real=R, seed=6000 + k, threshold=3.0)
+                pending[srv.submit(job)] = (t0 + times[k], (1 + R) * n * n * J, n, outs)
+            fin = srv.completed()
+            if fin:
+                done_at = time.perf_counter()
+            for t in fin:
+                arr, u, n, outs = pending.pop(t)
+                free[n].append(outs)
+                lat.append(done_at - arr)
+                units += u
+        span = done_at - t0
+        lat = np.array(lat) * 1e3
+        return {"requests": len(times), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "maps_per_s": len(times) / span,
+                "value": units / span / 1e6, "unit": "Mpix·scales/s"}
+
+    # warm up every size once, then the saturated burst
+    run(np.zeros(5), [256, 512, 1024, 2048, 4096])
+    _, sides = synth.served_stream(48, 1.0)
+    burst = run(np.zeros(48), sides)
+    mu = burst["maps_per_s"]
+    out = {"workload": "Poisson arrivals, float32 sides log-uniform 256..4096, J = min(9, log2 N - 2), "
+                       "R = 32 per request, 8 slots, footprint admission",
+           "saturated": burst, "levels": {}}
+    for frac in (0.5, 0.8):
+        qps = frac * mu
+        count = int(min(400, max(30, qps * level_seconds)))
+        times, sides = synth.served_stream(count, qps)
+        out["levels"]["%.1f_mu" % frac] = dict(run(times, sides), qps=qps)
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,7 +296,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle's timed sample (0 to skip)")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the uneven-batch measurement (for profiler runs)")
+                    help="skip the uneven-batch and served-stream measurements (profiler runs)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="length of each served-stream level")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -326,10 +414,12 @@ def main():
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
-    batched = None
+    batched = served = None
     if not args.no_batched:
         print("bench: uneven batch", file=sys.stderr, flush=True)
         batched = uneven_batch(ctx, max(2, args.steps))
+        print("bench: served stream", file=sys.stderr, flush=True)
+        served = served_stream(ctx, args.serve_seconds)
 
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix·scales/s", "n_gpus": 1,
@@ -343,7 +433,8 @@ def main():
         "wall_s_timed": wall,
         "hbm_alg_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
                         / (HBM_PEAK_GBS * 1e9),
-        "plain": plain, "batched": batched, "roofline": roofline, "kernels": kernels,
+        "plain": plain, "batched": batched, "served": served, "roofline": roofline,
+        "kernels": kernels,
     }
     ctx.close()
     if args.cpu_seconds > 0:

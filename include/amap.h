@@ -50,7 +50,8 @@ typedef enum {
     AMAP_E_INVAL = 1,       /* invalid argument; nothing was enqueued        */
     AMAP_E_NOMEM = 2,       /* device memory for workspace unavailable       */
     AMAP_E_HIP = 3,         /* HIP runtime error (launch or asynchronous)    */
-    AMAP_E_UNSUPPORTED = 4  /* valid request this build does not handle      */
+    AMAP_E_UNSUPPORTED = 4, /* valid request this build does not handle      */
+    AMAP_E_BUSY = 5         /* server queue full; submit again later         */
 } amap_status;
 
 typedef enum { AMAP_F32 = 0, AMAP_F64 = 1 } amap_dtype;
@@ -66,6 +67,7 @@ typedef enum {
 
 typedef struct amap_ctx*  amap_ctx_t;
 typedef struct amap_plan* amap_plan_t;
+typedef struct amap_server* amap_server_t;
 
 /* Create a context on HIP device `hip_device`.  The context owns the
  * twiddle tables and a growable device workspace.  *out is set on success. */
@@ -234,6 +236,49 @@ amap_status amap_plan_destroy(amap_plan_t plan);
 /* Device bytes a job needs besides its own inputs and outputs (the unit an
  * admission policy budgets against). */
 size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real);
+
+/* ---- serving: continuous batching of independent jobs ---- */
+
+/* A request loop on one context.  The server allocates one arena of
+ * `mem_budget` bytes of device memory at creation.  Submitted jobs wait in a
+ * FIFO; the oldest is admitted when one of `max_inflight` slots is free and
+ * a free range of the arena holds its footprint (amap_job_footprint_bytes,
+ * first fit); nothing is allocated while serving.  Each slot owns a HIP
+ * stream (default priority), so admitted jobs run concurrently, and a
+ * finishing job returns its slot and range without synchronising the
+ * device.  Admission happens inside submit, poll
+ * and wait, so callers that keep submitting and polling get continuous
+ * batching.  A job's results are the same alone or in a mix: the kernels of
+ * a job read only its own inputs and workspace.  The job's buffers must stay
+ * valid until poll reports it done.  Calls on one server are not
+ * thread-safe. */
+amap_status amap_server_create(amap_ctx_t ctx, amap_dtype dt, size_t mem_budget,
+                               int max_inflight, int max_queued, amap_server_t* out);
+
+/* Validate and enqueue `job` (copied); `*ticket` identifies it.
+ * AMAP_E_NOMEM if its footprint alone exceeds the budget (never
+ * admissible); AMAP_E_BUSY if max_queued jobs already wait. */
+amap_status amap_server_submit(amap_server_t srv, const amap_job* job, long long* ticket);
+
+/* Admit what fits, then report whether `ticket` has finished (*done = 1;
+ * its outputs are then complete and visible to later work on any stream).
+ * AMAP_E_INVAL for an unknown ticket. */
+amap_status amap_server_poll(amap_server_t srv, long long ticket, int* done);
+
+/* Admit what fits, then write up to `cap` tickets that finished since the
+ * last call into `out` (oldest first) and their number into *count.  Lets a
+ * loop with many jobs outstanding poll once per iteration. */
+amap_status amap_server_completed(amap_server_t srv, long long* out, int cap, int* count);
+
+/* Block until `ticket` has finished. */
+amap_status amap_server_wait(amap_server_t srv, long long ticket);
+
+/* Jobs waiting, jobs on the device, and the admitted footprint in bytes. */
+amap_status amap_server_stats(amap_server_t srv, int* queued, int* inflight,
+                              size_t* mem_in_use);
+
+/* Finish all submitted work and release the server; NULL is accepted. */
+amap_status amap_server_destroy(amap_server_t srv);
 
 #ifdef __cplusplus
 }

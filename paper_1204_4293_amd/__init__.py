@@ -22,7 +22,8 @@ HEADER = os.path.join(ROOT, "include", "amap.h")
 F32, F64 = 0, 1
 FILTER_STARLET, FILTER_S98, FILTER_JBJ04 = 0, 1, 2
 _STATUS = {0: "AMAP_OK", 1: "AMAP_E_INVAL", 2: "AMAP_E_NOMEM", 3: "AMAP_E_HIP",
-           4: "AMAP_E_UNSUPPORTED"}
+           4: "AMAP_E_UNSUPPORTED", 5: "AMAP_E_BUSY"}
+E_NOMEM, E_BUSY = 2, 5
 
 _lib = None
 
@@ -82,6 +83,14 @@ def load():
         "amap_batch_run": (I, [P, P]),
         "amap_plan_destroy": (I, [P]),
         "amap_job_footprint_bytes": (ctypes.c_size_t, [I, I, I, I]),
+        "amap_server_create": (I, [P, I, ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
+        "amap_server_submit": (I, [P, ctypes.POINTER(AmapJob), ctypes.POINTER(ctypes.c_longlong)]),
+        "amap_server_poll": (I, [P, ctypes.c_longlong, ctypes.POINTER(I)]),
+        "amap_server_wait": (I, [P, ctypes.c_longlong]),
+        "amap_server_completed": (I, [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]),
+        "amap_server_stats": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+        "amap_server_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -245,6 +254,22 @@ class Context:
         return o
 
 
+def _fill_job(a, j):
+    """Fill an AmapJob from a dict of tensors; returns the tensors used."""
+    a.n = _side(j["g1"])
+    a.J = int(j["planes"].shape[0])
+    a.n_real = int(j.get("n_real", 0))
+    a.seed = int(j.get("seed", 0))
+    a.threshold = float(j.get("threshold", 3.0))
+    used = []
+    for key in ("g1", "g2", "kappa_e", "planes", "sigma", "snr", "peaks"):
+        t = j.get(key)
+        setattr(a, key, _ptr(t).value if t is not None else None)
+        if t is not None:
+            used.append(t)
+    return used
+
+
 class BatchPlan:
     """A batch of maps run as one unit (amap_batch_plan / amap_batch_run).
 
@@ -262,20 +287,9 @@ class BatchPlan:
         arr = (AmapJob * len(jobs))()
         self._keep = []
         for i, j in enumerate(jobs):
-            n = _side(j["g1"])
             if _dt(j["g1"]) != dt:
                 raise TypeError("all jobs of a plan share one dtype")
-            a = arr[i]
-            a.n = n
-            a.J = int(j["planes"].shape[0])
-            a.n_real = int(j.get("n_real", 0))
-            a.seed = int(j.get("seed", 0))
-            a.threshold = float(j.get("threshold", 3.0))
-            for key in ("g1", "g2", "kappa_e", "planes", "sigma", "snr", "peaks"):
-                t = j.get(key)
-                setattr(a, key, _ptr(t).value if t is not None else None)
-                if t is not None:
-                    self._keep.append(t)
+            self._keep += _fill_job(arr[i], j)
         self._jobs = arr
         h = ctypes.c_void_p()
         _check(load().amap_batch_plan(ctx._h, dt, arr, len(jobs), ctypes.byref(h)))
@@ -289,6 +303,68 @@ class BatchPlan:
         if self._h:
             load().amap_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (amap_server_*): jobs are admitted
+    by workspace footprint against ``mem_budget`` bytes into
+    ``max_inflight`` concurrent slots.  Jobs are dicts as for BatchPlan."""
+
+    def __init__(self, ctx, dtype=torch.float32, mem_budget=8 << 30, max_inflight=4,
+                 max_queued=4096):
+        dt = F32 if dtype == torch.float32 else F64
+        h = ctypes.c_void_p()
+        _check(load().amap_server_create(ctx._h, dt, int(mem_budget), int(max_inflight),
+                                         int(max_queued), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._held = {}
+
+    def submit(self, job):
+        a = AmapJob()
+        used = _fill_job(a, job)
+        t = ctypes.c_longlong()
+        _check(load().amap_server_submit(self._h, ctypes.byref(a), ctypes.byref(t)))
+        self._held[t.value] = used
+        return t.value
+
+    def poll(self, ticket):
+        d = ctypes.c_int()
+        _check(load().amap_server_poll(self._h, int(ticket), ctypes.byref(d)))
+        if d.value:
+            self._held.pop(ticket, None)
+        return bool(d.value)
+
+    def wait(self, ticket):
+        _check(load().amap_server_wait(self._h, int(ticket)))
+        self._held.pop(ticket, None)
+
+    def completed(self, cap=1024):
+        """Tickets finished since the last call (admits queued work first)."""
+        buf = (ctypes.c_longlong * cap)()
+        k = ctypes.c_int()
+        _check(load().amap_server_completed(self._h, buf, cap, ctypes.byref(k)))
+        done = list(buf[:k.value])
+        for t in done:
+            self._held.pop(t, None)
+        return done
+
+    def stats(self):
+        q, f, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(load().amap_server_stats(self._h, ctypes.byref(q), ctypes.byref(f), ctypes.byref(m)))
+        return {"queued": q.value, "inflight": f.value, "mem_in_use": m.value}
+
+    def close(self):
+        if self._h:
+            load().amap_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
 
     def __del__(self):
         try:

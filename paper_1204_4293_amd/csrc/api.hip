@@ -993,3 +993,260 @@ amap_status amap_plan_destroy(amap_plan_t p) {
 }
 
 }  // extern "C"
+
+// ---- serving ------------------------------------------------------------------------
+struct amap_server {
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        long long ticket = -1;    // job on the device, or -1
+        size_t footprint = 0;
+        size_t offset = 0;        // of its workspace in the arena
+    };
+    struct Pending {
+        long long ticket;
+        amap_job job;
+        size_t footprint;
+    };
+    amap_ctx* ctx = nullptr;
+    amap_dtype dt = AMAP_F32;
+    size_t budget = 0, in_use = 0;
+    int max_queued = 0;
+    long long next_ticket = 0;
+    std::vector<Slot> slots;
+    std::vector<Pending> queue;               // FIFO (front = oldest)
+    std::map<long long, int> state;           // 0 queued, 1 on the device, 2 done
+    std::vector<long long> finished;          // done, not yet reported by amap_server_completed
+    char* arena = nullptr;                    // mem_budget bytes of device memory, allocated once
+    std::map<size_t, size_t> holes;           // free ranges of the arena: offset -> length
+
+    // First fit of `bytes` (a multiple of 256) in the arena; false if no hole fits.
+    bool take(size_t bytes, size_t* off) {
+        for (auto it = holes.begin(); it != holes.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            holes.erase(it);
+            if (rest) holes[*off + bytes] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t bytes) {
+        auto it = holes.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != holes.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            holes.erase(nx);
+        }
+        if (it != holes.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                holes.erase(it);
+            }
+        }
+    }
+};
+
+namespace {
+
+// Enqueue one admitted job on its slot, its workspace at `off` in the arena.
+amap_status launch_on_slot(amap_server* v, amap_server::Slot& sl, const amap_server::Pending& p,
+                           size_t off) {
+    TimerScope ts(v->ctx);
+    char* w = v->arena + off;
+    AMAP_TRY(v->dt == AMAP_F32 ? enqueue_job<float>(v->ctx, w, p.job, sl.stream)
+                               : enqueue_job<double>(v->ctx, w, p.job, sl.stream));
+    AMAP_HIP(hipEventRecord(sl.done, sl.stream), "done event");
+    sl.ticket = p.ticket;
+    sl.footprint = p.footprint;
+    sl.offset = off;
+    v->in_use += p.footprint;
+    v->state[p.ticket] = 1;
+    return AMAP_OK;
+}
+
+// Retire finished slots, then admit queued jobs in order while a slot is
+// free and the budget allows (a job that does not fit blocks those behind it,
+// so large jobs are not starved).
+amap_status pump(amap_server* v) {
+    for (amap_server::Slot& sl : v->slots) {
+        if (sl.ticket < 0) continue;
+        const hipError_t e = hipEventQuery(sl.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return fail(AMAP_E_HIP, "job %lld: %s", sl.ticket, hipGetErrorString(e));
+        v->state[sl.ticket] = 2;
+        v->finished.push_back(sl.ticket);
+        v->in_use -= sl.footprint;
+        v->give(sl.offset, sl.footprint);
+        sl.ticket = -1;
+        sl.footprint = 0;
+    }
+    while (!v->queue.empty()) {
+        const amap_server::Pending& p = v->queue.front();
+        amap_server::Slot* free_slot = nullptr;
+        for (amap_server::Slot& sl : v->slots)
+            if (sl.ticket < 0) { free_slot = &sl; break; }
+        if (!free_slot) break;
+        size_t off = 0;
+        if (!v->take(p.footprint, &off)) break;  // wait for memory
+        const amap_status st = launch_on_slot(v, *free_slot, p, off);
+        if (st != AMAP_OK) {
+            v->give(off, p.footprint);
+            return st;
+        }
+        v->queue.erase(v->queue.begin());
+    }
+    return AMAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amap_status amap_server_create(amap_ctx_t c, amap_dtype dt, size_t mem_budget, int max_inflight,
+                               int max_queued, amap_server_t* out) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!out) return fail(AMAP_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    AMAP_TRY(check_dtype(dt));
+    if (max_inflight < 1 || max_inflight > 64)
+        return fail(AMAP_E_INVAL, "max_inflight must be in [1, 64] (got %d)", max_inflight);
+    if (max_queued < 1) return fail(AMAP_E_INVAL, "max_queued must be >= 1 (got %d)", max_queued);
+    if (mem_budget == 0) return fail(AMAP_E_INVAL, "mem_budget must be > 0");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    amap_server* v = new (std::nothrow) amap_server;
+    if (!v) return fail(AMAP_E_NOMEM, "out of host memory");
+    v->ctx = c;
+    v->dt = dt;
+    v->max_queued = max_queued;
+    v->slots.resize(max_inflight);
+    // one arena for all admitted workspaces: no allocation while serving
+    v->budget = mem_budget / 256 * 256;
+    if (v->budget == 0 || hipMalloc(&v->arena, v->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        delete v;
+        return fail(AMAP_E_NOMEM, "cannot allocate the %zu-byte server arena", mem_budget);
+    }
+    v->holes[0] = v->budget;
+    for (amap_server::Slot& sl : v->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            for (amap_server::Slot& t : v->slots) {
+                if (t.done) (void)hipEventDestroy(t.done);
+                if (t.stream) (void)hipStreamDestroy(t.stream);
+            }
+            (void)hipFree(v->arena);
+            delete v;
+            return fail(AMAP_E_HIP, "cannot create server streams");
+        }
+    }
+    *out = v;
+    return AMAP_OK;
+}
+
+amap_status amap_server_submit(amap_server_t v, const amap_job* job, long long* ticket) {
+    g_last_error.clear();
+    if (!v) return fail(AMAP_E_INVAL, "server must not be NULL");
+    if (!job || !ticket) return fail(AMAP_E_INVAL, "job and ticket must not be NULL");
+    AMAP_TRY(validate_job(v->dt, *job));
+    if (job->n_real == 1 || job->n_real < 0)
+        return fail(AMAP_E_INVAL, "n_real must be 0 or >= 2 (got %d)", job->n_real);
+    const size_t fp = align256(job_workspace_bytes(v->dt, *job));
+    if (fp > v->budget)
+        return fail(AMAP_E_NOMEM, "job needs %zu bytes of workspace, over the budget of %zu", fp,
+                    v->budget);
+    DeviceGuard g(v->ctx->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", v->ctx->device);
+    AMAP_TRY(pump(v));
+    if ((int)v->queue.size() >= v->max_queued) return fail(AMAP_E_BUSY, "queue full");
+    const long long t = v->next_ticket++;
+    v->queue.push_back(amap_server::Pending{t, *job, fp});
+    v->state[t] = 0;
+    *ticket = t;
+    return pump(v);
+}
+
+amap_status amap_server_poll(amap_server_t v, long long ticket, int* done) {
+    g_last_error.clear();
+    if (!v || !done) return fail(AMAP_E_INVAL, "server and done must not be NULL");
+    auto it = v->state.find(ticket);
+    if (it == v->state.end()) return fail(AMAP_E_INVAL, "unknown ticket %lld", ticket);
+    DeviceGuard g(v->ctx->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", v->ctx->device);
+    AMAP_TRY(pump(v));
+    *done = v->state[ticket] == 2;
+    return AMAP_OK;
+}
+
+amap_status amap_server_completed(amap_server_t v, long long* out, int cap, int* count) {
+    g_last_error.clear();
+    if (!v || !count || (cap > 0 && !out)) return fail(AMAP_E_INVAL, "bad arguments");
+    DeviceGuard g(v->ctx->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", v->ctx->device);
+    AMAP_TRY(pump(v));
+    std::sort(v->finished.begin(), v->finished.end());
+    const int k = std::min<int>(cap, (int)v->finished.size());
+    for (int i = 0; i < k; ++i) out[i] = v->finished[i];
+    v->finished.erase(v->finished.begin(), v->finished.begin() + k);
+    *count = k;
+    return AMAP_OK;
+}
+
+amap_status amap_server_wait(amap_server_t v, long long ticket) {
+    g_last_error.clear();
+    if (!v) return fail(AMAP_E_INVAL, "server must not be NULL");
+    if (v->state.find(ticket) == v->state.end()) return fail(AMAP_E_INVAL, "unknown ticket %lld", ticket);
+    DeviceGuard g(v->ctx->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", v->ctx->device);
+    for (;;) {
+        AMAP_TRY(pump(v));
+        if (v->state[ticket] == 2) return AMAP_OK;
+        // block on the oldest job on the device, then retire and admit again
+        amap_server::Slot* busy = nullptr;
+        for (amap_server::Slot& sl : v->slots)
+            if (sl.ticket >= 0 && (!busy || sl.ticket < busy->ticket)) busy = &sl;
+        if (!busy) return fail(AMAP_E_HIP, "ticket %lld cannot be admitted", ticket);
+        const hipError_t e = hipEventSynchronize(busy->done);
+        if (e != hipSuccess)
+            return fail(AMAP_E_HIP, "wait for job %lld: %s", busy->ticket, hipGetErrorString(e));
+    }
+}
+
+amap_status amap_server_stats(amap_server_t v, int* queued, int* inflight, size_t* mem_in_use) {
+    g_last_error.clear();
+    if (!v) return fail(AMAP_E_INVAL, "server must not be NULL");
+    int n = 0;
+    for (const amap_server::Slot& sl : v->slots) n += sl.ticket >= 0;
+    if (queued) *queued = (int)v->queue.size();
+    if (inflight) *inflight = n;
+    if (mem_in_use) *mem_in_use = v->in_use;
+    return AMAP_OK;
+}
+
+amap_status amap_server_destroy(amap_server_t v) {
+    g_last_error.clear();
+    if (!v) return AMAP_OK;
+    DeviceGuard g(v->ctx->device);
+    amap_status st = AMAP_OK;
+    // run what is still queued, then drain
+    while (st == AMAP_OK && !v->queue.empty()) {
+        st = pump(v);
+        for (amap_server::Slot& sl : v->slots)
+            if (sl.ticket >= 0) (void)hipEventSynchronize(sl.done);
+    }
+    for (amap_server::Slot& sl : v->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    if (v->arena) (void)hipFree(v->arena);
+    delete v;
+    return st;
+}
+
+}  // extern "C"
+
