@@ -86,6 +86,19 @@ amap_status amap_sync(amap_ctx_t ctx, void* stream);
 /* Bytes of workspace the context currently holds on the device. */
 size_t amap_workspace_bytes(amap_ctx_t ctx);
 
+/* Tile autotuning (on by default).  The first starlet transform of each
+ * shape (element type, n, J, signal or noise statistics, batch) on a stream
+ * that is not being captured times the candidate LDS tiles of every stage
+ * start and scale count on the call's own buffers and keeps, per context,
+ * the schedule of least total time (dynamic programming over the stage
+ * starts); later calls of that shape reuse it.  Batch plans tune at
+ * creation with one direct run of the plan.  Results do not depend on the
+ * schedule except, for noise statistics, in the rounding of how per-group
+ * partial statistics are merged.  enable = 0 uses the analytic planner
+ * (fewest stages, least halo overhead) and keeps existing tuned schedules
+ * unused until it is enabled again. */
+amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
+
 /* Per-kernel timing (diagnostics): while enabled, every kernel the context
  * launches is bracketed by two HIP events recorded on the launch's stream.
  * Work captured into a batch plan's graph is not timed. */

@@ -69,6 +69,7 @@ def load():
         "amap_sync": (I, [P, P]),
         "amap_workspace_bytes": (ctypes.c_size_t, [P]),
         "amap_timing_enable": (I, [P, I]),
+        "amap_set_autotune": (I, [P, I]),
         "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
         "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
@@ -161,6 +162,9 @@ class Context:
 
     def sync(self):
         _check(load().amap_sync(self._h, _stream()))
+
+    def set_autotune(self, enable=True):
+        _check(load().amap_set_autotune(self._h, 1 if enable else 0))
 
     def timing_enable(self, enable=True):
         _check(load().amap_timing_enable(self._h, 1 if enable else 0))

@@ -64,6 +64,14 @@ template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 //                       `done` realisations merged so far; planes unused
 // Scratch (each batch*n*n): cbuf0 (always), cbuf1 (ACC), tmp; wbuf (ACC):
 // 3*batch*n*n, the detail planes of one stage.
+// A starlet stage schedule: stage k covers scales st[k].j0 .. j0+ns-1 with
+// an LDS tile of tw pixels by th sub-rows.  nstages == 0: use the analytic
+// planner.
+struct StagePlan {
+    int nstages = 0;
+    struct Stage { int j0, ns, tw, th; } st[16];
+};
+
 template <typename T>
 struct StarletArgs {
     int logn, J, batch, done;
@@ -84,6 +92,7 @@ struct StarletArgs {
     // cbuf0 and cbuf1 and a tiled plan
     const long long* kappa_off = nullptr;
     const long long* planes_off = nullptr;
+    const StagePlan* plan = nullptr;  // tuned schedule, or null for the analytic one
 };
 // Bytes of per-group partial statistics a noise batch may need.
 size_t starlet_partials_bytes(int logn, int batch);
@@ -91,6 +100,11 @@ template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
 // True when every stage of an n x n, J-plane transform has an LDS tile
 // (grouped maps need it).
 template <typename T> bool starlet_all_tiled(int n, int J);
+// Times candidate tiles of every stage start and scale count on a's buffers
+// (reps launches each, on a.stream, synchronously) and picks the schedule of
+// least total time by dynamic programming over the stage starts.  Writes
+// garbage into a's outputs and, for noise statistics, into M and M2.
+template <typename T> hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out);
 template <typename T>
 hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStream_t s);
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
@@ -163,7 +164,36 @@ struct amap_ctx {
     cpx<double>* tw64 = nullptr;
     Workspace ws;
     EventTimer* timer = nullptr;
+    // tuned starlet schedules: (element size, log2 n, J, noise mode, batch) -> plan
+    // (nstages == 0: the analytic planner)
+    mutable std::map<std::array<int, 5>, StagePlan> plans;
+    bool autotune = true;
 };
+
+namespace {
+// The tuned schedule for a starlet launch shaped like `a`, tuning it on a's
+// buffers on first use (which overwrites a's outputs and, in noise mode, M
+// and M2: callers tune before they zero the statistics).  Never tunes while
+// the stream is being captured; then the analytic plan is used.
+template <typename T>
+const StagePlan* tuned_plan(const amap_ctx* c, const StarletArgs<T>& a) {
+    if (!c->autotune) return nullptr;
+    const std::array<int, 5> key{(int)sizeof(T), a.logn, a.J, a.M != nullptr, a.batch};
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) return &it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(a.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    StagePlan p;
+    if (tune_starlet<T>(a, 3, &p) != hipSuccess) {
+        (void)hipGetLastError();
+        p.nstages = 0;
+    }
+    return &(c->plans[key] = p);
+}
+}  // namespace
 
 namespace {
 // Installs the context's timer (if any) for the calling thread.
@@ -284,14 +314,16 @@ amap_status enqueue_ks(const amap_ctx* ctx, int logn, int batch, const T* g1, co
 // Signal-path starlet: `scratch` holds 2*batch*n*n elements (c ping-pong
 // buffer and the per-scale row-pass scratch).
 template <typename T>
-amap_status enqueue_starlet(int logn, int J, int batch, const T* kappa, long long in_stride,
-                            T* planes, long long planes_stride, T* scratch, hipStream_t s) {
+amap_status enqueue_starlet(const amap_ctx* ctx, int logn, int J, int batch, const T* kappa,
+                            long long in_stride, T* planes, long long planes_stride, T* scratch,
+                            hipStream_t s) {
     const long long n2 = 1ll << (2 * logn);
     StarletArgs<T> a;
     a.logn = logn; a.J = J; a.batch = batch; a.done = 0; a.kappa = kappa; a.in_stride = in_stride;
     a.planes = planes; a.planes_stride = planes_stride;
     a.cbuf0 = scratch; a.cbuf1 = nullptr; a.tmp = scratch + (long long)batch * n2; a.wbuf = nullptr;
     a.M = nullptr; a.M2 = nullptr; a.part = nullptr; a.stream = s;
+    a.plan = tuned_plan<T>(ctx, a);
     AMAP_HIP(launch_starlet<T>(a), "starlet kernels");
     return AMAP_OK;
 }
@@ -333,6 +365,13 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
     void* part = p;                              p += align256(starlet_partials_bytes(logn, B));
     double* M = reinterpret_cast<double*>(p);    p += align256((size_t)(J - 1) * n2 * 8);
     double* M2 = reinterpret_cast<double*>(p);
+    // the schedule of a full batch serves every batch; it is tuned (if new)
+    // before the statistics are zeroed
+    StarletArgs<T> t;
+    t.logn = logn; t.J = J; t.batch = B; t.done = 0; t.kappa = kap; t.in_stride = n2;
+    t.planes = nullptr; t.planes_stride = 0; t.cbuf0 = cb0; t.cbuf1 = cb1; t.tmp = tmp;
+    t.wbuf = wb; t.M = M; t.M2 = M2; t.part = part; t.stream = s;
+    const StagePlan* plan = tuned_plan<T>(ctx, t);
     AMAP_HIP(launch_zero_f64(M, (long long)(J - 1) * n2, s), "zero accumulators");
     AMAP_HIP(launch_zero_f64(M2, (long long)(J - 1) * n2, s), "zero accumulators");
     for (int r0 = 0; r0 < n_real; r0 += B) {
@@ -342,7 +381,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
         StarletArgs<T> a;
         a.logn = logn; a.J = J; a.batch = bb; a.done = r0; a.kappa = kap; a.in_stride = n2;
         a.planes = nullptr; a.planes_stride = 0; a.cbuf0 = cb0; a.cbuf1 = cb1; a.tmp = tmp;
-        a.wbuf = wb; a.M = M; a.M2 = M2; a.part = part; a.stream = s;
+        a.wbuf = wb; a.M = M; a.M2 = M2; a.part = part; a.stream = s; a.plan = plan;
         AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
     AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s),
@@ -418,6 +457,13 @@ amap_status amap_timing_enable(amap_ctx_t c, int enable) {
         delete c->timer;
         c->timer = nullptr;
     }
+    return AMAP_OK;
+}
+
+amap_status amap_set_autotune(amap_ctx_t c, int enable) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    c->autotune = enable != 0;
     return AMAP_OK;
 }
 
@@ -508,9 +554,9 @@ amap_status amap_starlet_forward(amap_ctx_t c, amap_dtype dt, int n, int J, cons
     const int logn = ilog2(n);
     const long long n2 = (long long)n * n;
     if (dt == AMAP_F32)
-        return enqueue_starlet<float>(logn, J, 1, (const float*)kappa, n2, (float*)planes,
+        return enqueue_starlet<float>(c, logn, J, 1, (const float*)kappa, n2, (float*)planes,
                                       (long long)J * n2, (float*)c->ws.ptr, s);
-    return enqueue_starlet<double>(logn, J, 1, (const double*)kappa, n2, (double*)planes,
+    return enqueue_starlet<double>(c, logn, J, 1, (const double*)kappa, n2, (double*)planes,
                                    (long long)J * n2, (double*)c->ws.ptr, s);
 }
 
@@ -720,7 +766,7 @@ static amap_status enqueue_job(const amap_ctx* c, char* w, const amap_job& j, hi
     char* nws = w + align256(2 * plane) + align256(plane) + align256(2 * plane);
     AMAP_TRY(enqueue_ks<T>(c, logn, 1, (const T*)j.g1, (const T*)j.g2, 0, C, kap, nullptr, n2,
                            false, 0, 0, s));
-    AMAP_TRY(enqueue_starlet<T>(logn, j.J, 1, kap, n2, (T*)j.planes, (long long)j.J * n2, tmp, s));
+    AMAP_TRY(enqueue_starlet<T>(c, logn, j.J, 1, kap, n2, (T*)j.planes, (long long)j.J * n2, tmp, s));
     if (j.n_real < 2) return AMAP_OK;
     AMAP_TRY(enqueue_noise<T>(c, nws, j.n, j.J, (const T*)j.g1, (const T*)j.g2, j.n_real, j.seed,
                               (const T*)j.planes, (T*)j.sigma, (T*)j.snr, s));
@@ -840,6 +886,7 @@ static amap_status enqueue_chunk(const amap_plan* p, const PlanChunk& ch, hipStr
     a.tmp = nullptr; a.wbuf = nullptr; a.M = nullptr; a.M2 = nullptr; a.part = nullptr; a.stream = s;
     a.kappa_off = off + 2 * ch.count;
     a.planes_off = off + 3 * ch.count;
+    a.plan = tuned_plan<T>(p->ctx, a);
     AMAP_HIP(launch_starlet<T>(a), "starlet kernels (grouped)");
     return AMAP_OK;
 }
@@ -936,6 +983,13 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
         } else if (hipMemcpy(p->tabs, host.data(), tab_bytes, hipMemcpyHostToDevice) != hipSuccess) {
             st = fail(AMAP_E_HIP, "cannot upload map tables");
         }
+    }
+    if (st == AMAP_OK && c->autotune) {
+        // one direct run on the null stream tunes (and caches) the starlet
+        // schedule of every group and job shape before any graph capture
+        st = enqueue_plan(p, nullptr);
+        if (st == AMAP_OK && hipDeviceSynchronize() != hipSuccess)
+            st = fail(AMAP_E_HIP, "plan warm-up run failed");
     }
     if (st != AMAP_OK) {
         if (p->tabs) (void)hipFree(p->tabs);

@@ -572,48 +572,70 @@ struct StageGeom {
 // Largest tile overhead accepted for a stage (LDS elements per output pixel).
 constexpr double kMaxHaloRatio = 2.6;
 
-// Picks the scale count and tile of the stage starting at scale j0 (at most
-// `left` scales remain): the largest ns <= 3 with a tile whose two buffers fit
-// in LDS and whose halo overhead is bounded; among those, the smallest
-// overhead.  Returns false if no tile exists even for one scale.
+// Tiles for a stage of ns scales from j0 whose two LDS buffers fit and whose
+// halo overhead is bounded, best first (smallest overhead, then least LDS);
+// noise stages also need the tile to fit the prefetch registers and one
+// owned vector per thread.  Returns the number written to out (at most cap).
 template <typename T>
-static bool pick_stage(int n, int j0, int left, bool noise, StageGeom* g) {
+static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, int cap) {
     constexpr int G = Vec<T>::G;
     const int d0 = 1 << (j0 - 1);
-    for (int ns = left < 3 ? left : 3; ns >= 1; --ns) {
-        const int Hx = stage_hx(d0, ns, G), Hv = 2 * ((1 << ns) - 1);
-        bool found = false;
-        StageGeom best{};
-        double best_ratio = 0.0;
-        for (int tw = 256; tw >= 16; tw /= 2) {
-            for (int th = 64; th >= 2; th /= 2) {
-                if (tw > n || th > n / d0) continue;
-                const int TXT = tw + 2 * Hx, TVT = th + 2 * Hv;
-                const size_t lds = 2 * (size_t)(TXT + 2 * G) * TVT * sizeof(T) + G * sizeof(T);
-                if (lds > (size_t)kLdsBytes) continue;
-                const double ratio = (double)TXT * TVT / ((double)tw * th);
-                if (ratio > kMaxHaloRatio && !(ns == 1 && ratio <= 2 * kMaxHaloRatio)) continue;
-                int nt = tw * th / (G * kVecPerThread);
-                nt = nt < 256 ? 256 : (nt > 512 ? 512 : nt);
-                if (tw * th > nt * G * kVecPerThread) continue;
-                if (noise) {
-                    if ((TXT / G) * TVT > nt * kPrefetch) continue;  // prefetch registers
-                    if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per thread
-                }
-                // prefer small overhead, then more workgroups per CU (less LDS)
-                if (!found || ratio < best_ratio - 1e-9 ||
-                    (ratio < best_ratio + 1e-9 && lds < best.lds)) {
-                    best = StageGeom{ns, nt, tw, th, lds};
-                    best_ratio = ratio;
-                    found = true;
-                }
+    const int Hx = stage_hx(d0, ns, G), Hv = 2 * ((1 << ns) - 1);
+    StageGeom all[48];
+    double ratio[48];
+    int m = 0;
+    for (int tw = 256; tw >= 16; tw /= 2) {
+        for (int th = 64; th >= 2; th /= 2) {
+            if (tw > n || th > n / d0) continue;
+            const int TXT = tw + 2 * Hx, TVT = th + 2 * Hv;
+            const size_t lds = 2 * (size_t)(TXT + 2 * G) * TVT * sizeof(T) + G * sizeof(T);
+            if (lds > (size_t)kLdsBytes) continue;
+            const double r = (double)TXT * TVT / ((double)tw * th);
+            if (r > kMaxHaloRatio && !(ns == 1 && r <= 2 * kMaxHaloRatio)) continue;
+            int nt = tw * th / (G * kVecPerThread);
+            nt = nt < 256 ? 256 : (nt > 512 ? 512 : nt);
+            if (tw * th > nt * G * kVecPerThread) continue;
+            if (noise) {
+                if ((TXT / G) * TVT > nt * kPrefetch) continue;  // prefetch registers
+                if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per thread
             }
-        }
-        if (found) {
-            *g = best;
-            return true;
+            // insertion by (overhead, LDS)
+            int k = m++;
+            while (k > 0 && (r < ratio[k - 1] - 1e-9 ||
+                             (r < ratio[k - 1] + 1e-9 && lds < all[k - 1].lds))) {
+                all[k] = all[k - 1];
+                ratio[k] = ratio[k - 1];
+                --k;
+            }
+            all[k] = StageGeom{ns, nt, tw, th, lds};
+            ratio[k] = r;
         }
     }
+    const int c = m < cap ? m : cap;
+    for (int i = 0; i < c; ++i) out[i] = all[i];
+    return c;
+}
+
+// Picks the scale count and tile of the stage starting at scale j0 (at most
+// `left` scales remain): the largest ns <= 3 that has a tile, with its best
+// tile.  Returns false if no tile exists even for one scale.
+template <typename T>
+static bool pick_stage(int n, int j0, int left, bool noise, StageGeom* g) {
+    for (int ns = left < 3 ? left : 3; ns >= 1; --ns)
+        if (stage_candidates<T>(n, j0, ns, noise, g, 1) == 1) return true;
+    return false;
+}
+
+// The geometry of a given tile (as the planner would size it).
+template <typename T>
+static bool stage_geom_of(int n, int j0, int ns, int tw, int th, bool noise, StageGeom* g) {
+    StageGeom all[48];
+    const int m = stage_candidates<T>(n, j0, ns, noise, all, 48);
+    for (int i = 0; i < m; ++i)
+        if (all[i].tw == tw && all[i].th == th) {
+            *g = all[i];
+            return true;
+        }
     return false;
 }
 
@@ -764,22 +786,32 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     struct Stage { int j0, ns; StageGeom g; bool tiled; };
     Stage plan[16];
     int nstages = 0;
-    for (int j0 = 1; j0 < a.J; ) {
-        StageGeom g{};
-        const bool tiled = pick_stage<T>(n, j0, a.J - j0, acc, &g);
-        const int ns = tiled ? g.ns : 1;
-        plan[nstages++] = Stage{j0, ns, g, tiled};
-        j0 += ns;
+    if (a.plan && a.plan->nstages > 0) {
+        // a tuned schedule (possibly a single stage, for timing it)
+        for (int k = 0; k < a.plan->nstages; ++k) {
+            const StagePlan::Stage& t = a.plan->st[k];
+            StageGeom g{};
+            if (!stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, acc, &g)) return hipErrorInvalidValue;
+            plan[nstages++] = Stage{t.j0, t.ns, g, true};
+        }
+    } else {
+        for (int j0 = 1; j0 < a.J; ) {
+            StageGeom g{};
+            const bool tiled = pick_stage<T>(n, j0, a.J - j0, acc, &g);
+            const int ns = tiled ? g.ns : 1;
+            plan[nstages++] = Stage{j0, ns, g, tiled};
+            j0 += ns;
+        }
     }
     if (a.planes_off) {
         // grouped maps: c ping-pongs between cbuf0 and cbuf1; the last stage
         // writes c_{J-1} into each map's last plane
-        if (acc || !a.kappa_off || !a.cbuf0 || !a.cbuf1) return hipErrorInvalidValue;
-        const T* cur = nullptr;
+        if (acc || !a.cbuf0 || !a.cbuf1) return hipErrorInvalidValue;
+        const T* cur = a.kappa_off ? nullptr : a.kappa;  // keeps the first stage's output off its input
         for (int gi = 0; gi < nstages; ++gi) {
             const Stage& st = plan[gi];
             if (!st.tiled) return hipErrorNotSupported;
-            const bool last = gi == nstages - 1;
+            const bool last = st.j0 + st.ns == a.J;
             int lt = 0;
             while ((1 << lt) < st.g.tw) ++lt;
             StageArgs<T> s;
@@ -801,7 +833,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     if (acc && a.in_stride != n2) return hipErrorInvalidValue;  // realisations are packed
     for (int gi = 0; gi < nstages; ++gi) {
         const Stage& st = plan[gi];
-        const bool last = gi == nstages - 1;
+        const bool last = st.j0 + st.ns == a.J;
         T* dst;
         long long dst_stride;
         if (!acc) {
@@ -888,6 +920,64 @@ hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStrea
                 k_reconstruct<T><<<(unsigned)((n2 + 255) / 256), 256, 0, s>>>(planes, out, logn, J));
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
+    const int n = 1 << a.logn, J = a.J;
+    const bool acc = a.M != nullptr;
+    if (J < 2 || J > 16 || reps < 1) return hipErrorInvalidValue;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(a.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return hipErrorNotSupported;  // timing needs a live stream
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // best[j]: least time for scales j .. J-1; pick[j]: its first stage
+    float best[18];
+    StagePlan::Stage pick[18];
+    best[J] = 0.f;
+    for (int j = J - 1; j >= 1 && e == hipSuccess; --j) {
+        best[j] = -1.f;
+        for (int ns = 1; ns <= 3 && j + ns <= J && e == hipSuccess; ++ns) {
+            if (best[j + ns] < 0.f) continue;
+            StageGeom cand[4];
+            const int nc = stage_candidates<T>(n, j, ns, acc, cand, 4);
+            for (int c = 0; c < nc && e == hipSuccess; ++c) {
+                StagePlan sub;
+                sub.nstages = 1;
+                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th};
+                StarletArgs<T> b = a;
+                b.plan = &sub;
+                if (j > 1 && b.planes_off) {  // grouped: later stages read the c buffers
+                    b.kappa = b.cbuf0;
+                    b.kappa_off = nullptr;
+                }
+                e = launch_starlet<T>(b);       // warm
+                if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_starlet<T>(b);
+                if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) break;
+                const float t = ms / reps + best[j + ns];
+                if (best[j] < 0.f || t < best[j]) {
+                    best[j] = t;
+                    pick[j] = sub.st[0];
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    if (best[1] < 0.f) return hipErrorNotSupported;  // some stage start has no tile
+    out->nstages = 0;
+    for (int j = 1; j < J; j += pick[j].ns) out->st[out->nstages++] = pick[j];
+    return hipSuccess;
+}
+template hipError_t tune_starlet<float>(const StarletArgs<float>&, int, StagePlan*);
+template hipError_t tune_starlet<double>(const StarletArgs<double>&, int, StagePlan*);
 
 template hipError_t launch_starlet<float>(const StarletArgs<float>&);
 template hipError_t launch_starlet<double>(const StarletArgs<double>&);

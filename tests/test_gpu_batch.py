@@ -163,3 +163,26 @@ def test_plan_rejects_bad_jobs(ctx):
     with pytest.raises(amap.AmapError):
         amap.BatchPlan(ctx, [{"g1": g, "g2": g, "n_real": 1,
                               "planes": torch.empty((3, 64, 64), device="cuda")}])
+
+
+@pytest.mark.parametrize("n,J", [(256, 6), (1024, 7), (2048, 9)])
+def test_autotuned_schedule_matches_analytic(ctx, n, J):
+    # tiles and stage splits change only the order of independent work:
+    # the starlet planes are bit-identical, noise statistics agree to rounding
+    print("autotune vs analytic n=%d J=%d" % (n, J), flush=True)
+    plain = amap.Context(0)
+    plain.set_autotune(False)
+    kappa = S.grf_kappa(n, 60 + J)
+    k = dev(kappa, torch.float32)
+    a = ctx.starlet_forward(k, J)
+    b = plain.starlet_forward(k, J)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    if n <= 1024:
+        _, g1, g2 = S.shear_map(n, 70 + J, 71 + J)
+        t1, t2 = dev(g1, torch.float32), dev(g2, torch.float32)
+        sa, _ = ctx.noise_maps(t1, t2, J, 40, 9, want_snr=False)
+        sb, _ = plain.noise_maps(t1, t2, J, 40, 9, want_snr=False)
+        torch.cuda.synchronize()
+        assert float((sa.double() - sb.double()).abs().max()) <= 1e-6 * float(sb.double().abs().max())
+    plain.close()
