@@ -70,6 +70,7 @@ def load():
         "amap_workspace_bytes": (ctypes.c_size_t, [P]),
         "amap_timing_enable": (I, [P, I]),
         "amap_set_autotune": (I, [P, I]),
+        "amap_plans_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
         "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
         "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
@@ -162,6 +163,13 @@ class Context:
 
     def sync(self):
         _check(load().amap_sync(self._h, _stream()))
+
+    def plans(self):
+        """The context's tuned starlet schedules (list of dicts)."""
+        import json
+        buf = ctypes.create_string_buffer(1 << 18)
+        _check(load().amap_plans_read(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def set_autotune(self, enable=True):
         _check(load().amap_set_autotune(self._h, 1 if enable else 0))

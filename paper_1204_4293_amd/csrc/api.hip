@@ -460,6 +460,34 @@ amap_status amap_timing_enable(amap_ctx_t c, int enable) {
     return AMAP_OK;
 }
 
+amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!buf || len == 0) return fail(AMAP_E_INVAL, "buf must not be NULL");
+    std::string out = "[";
+    bool first = true;
+    for (const auto& kv : c->plans) {
+        char item[160];
+        snprintf(item, sizeof item, "%s{\"elem\": %d, \"logn\": %d, \"J\": %d, \"noise\": %d, \"batch\": %d, \"stages\": [",
+                 first ? "" : ", ", kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4]);
+        out += item;
+        for (int k = 0; k < kv.second.nstages; ++k) {
+            const StagePlan::Stage& t = kv.second.st[k];
+            snprintf(item, sizeof item, "%s[%d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th);
+            out += item;
+        }
+        out += "]}";
+        first = false;
+    }
+    out += "]";
+    if (out.size() + 1 > len) {
+        buf[0] = 0;
+        return fail(AMAP_E_INVAL, "buffer too small: need %zu bytes", out.size() + 1);
+    }
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return AMAP_OK;
+}
+
 amap_status amap_set_autotune(amap_ctx_t c, int enable) {
     g_last_error.clear();
     if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");

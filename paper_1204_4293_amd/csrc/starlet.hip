@@ -111,10 +111,24 @@ constexpr int kSegLen = 4;        // column-pass outputs per sliding window
 constexpr int kVecPerThread = 2;  // owned output vectors per thread
 constexpr int kPrefetch = 6;      // tile vectors per thread held while prefetching
 
-// Prefetch registers of a noise-stage thread.  The planner bounds a tile's
-// vectors by 6 per write-kernel thread (at most 512 threads), so 1024-thread
-// noise stages need only 3, which keeps them within 128 VGPRs.
-__host__ __device__ constexpr int noise_prefetch(int nt) { return nt >= 1024 ? 3 : kPrefetch; }
+// Noise stages: NT threads, each owning KV output vectors (its Welford state
+// lives in registers).  Tiles of up to 1024 vectors run one vector per
+// thread (256, 512 or 1024 threads); tiles of 2048 vectors run 512 threads
+// with four vectors each, which fits the larger state of one or two scales
+// in the 256 registers a thread of a 512-thread workgroup may hold.
+struct NoiseCfg { int nt, kv; };
+__host__ __device__ constexpr NoiseCfg noise_cfg(int vec) {
+    return vec <= 256 ? NoiseCfg{256, 1}
+         : vec <= 512 ? NoiseCfg{512, 1}
+         : vec <= 1024 ? NoiseCfg{1024, 1}
+         : NoiseCfg{512, 4};
+}
+// Prefetch registers (16-byte vectors) per thread: a tile's vectors may not
+// exceed nt times this.  One-vector stages keep 3 (their 128-register
+// budget); four-vector stages hold 8.
+__host__ __device__ constexpr int noise_prefetch(int nt, int kv) {
+    return kv > 1 ? 8 : 3;
+}
 
 // Barrier that orders only LDS accesses, so global loads issued before it
 // (the next tile's prefetch) stay in flight across it.
@@ -359,8 +373,12 @@ struct NoiseStageArgs {
     float inv_tvec;          // 1 / (vectors per tile row), for index splitting
 };
 
-template <typename T, int NT, int NS>
-__global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a) {
+// Single-precision one-vector stages of 256 or 512 threads keep to 128
+// registers, so that two or more workgroups share a CU and overlap each
+// other's barrier phases.
+template <typename T, int NT, int NS, int KV>
+__global__ void __launch_bounds__(NT, (sizeof(T) == 4 && KV == 1 && NT <= 512) ? 4 : 1)
+k_starlet_noise_stage(NoiseStageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
@@ -374,15 +392,23 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
     const int tvec = g.TXT / G;
     const int nload = tvec * g.TVT;
 
-    constexpr int PF = noise_prefetch(NT);
+    constexpr int PF = noise_prefetch(NT, KV);
     VA pf[PF];
-    AccT mean[NS][G], m2[NS][G];
+    AccT mean[NS][KV][G], m2[NS][KV][G];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int c = 0; c < G; ++c) mean[s][c] = m2[s][c] = (AccT)0;
-    const bool owner = (int)threadIdx.x < g.nvec;
-    const int own_e = threadIdx.x * G;
+        for (int k = 0; k < KV; ++k)
+#pragma unroll
+            for (int c = 0; c < G; ++c) mean[s][k][c] = m2[s][k][c] = (AccT)0;
+    // owned vectors threadIdx.x + k*NT, k < KV
+    bool owner[KV];
+    int own_e[KV];
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+        owner[k] = (int)threadIdx.x + k * NT < g.nvec;
+        own_e[k] = ((int)threadIdx.x + k * NT) * G;
+    }
 
     // first tile
     if (count > 0) {
@@ -419,44 +445,56 @@ __global__ void __launch_bounds__(NT) k_starlet_noise_stage(NoiseStageArgs<T> a)
             }
         }
         lds_barrier();
-        VA prev;
-        if (owner) prev = vload<T, G>(A + owned_lds(g, own_e));
+        VA prev[KV];
+#pragma unroll
+        for (int k = 0; k < KV; ++k)
+            if (owner[k]) prev[k] = vload<T, G>(A + owned_lds(g, own_e[k]));
         const AccT inv = (AccT)1 / (AccT)(it + 1);
         int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
             tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
-            if (owner) {
-                const VA c = vload<T, G>(A + owned_lds(g, own_e));
+#pragma unroll
+            for (int k = 0; k < KV; ++k) {
+                if (!owner[k]) continue;
+                const VA c = vload<T, G>(A + owned_lds(g, own_e[k]));
 #pragma unroll
                 for (int cc = 0; cc < G; ++cc) {
-                    const AccT x = (AccT)(prev.e[cc] - c.e[cc]);
-                    const AccT d = x - mean[s][cc];
-                    mean[s][cc] = fma(d, inv, mean[s][cc]);
-                    m2[s][cc] = fma(d, x - mean[s][cc], m2[s][cc]);
+                    const AccT x = (AccT)(prev[k].e[cc] - c.e[cc]);
+                    const AccT d = x - mean[s][k][cc];
+                    mean[s][k][cc] = fma(d, inv, mean[s][k][cc]);
+                    m2[s][k][cc] = fma(d, x - mean[s][k][cc], m2[s][k][cc]);
                 }
-                prev = c;
+                prev[k] = c;
             }
         }
-        if (a.cout && owner) vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e), prev);
+        if (a.cout) {
+#pragma unroll
+            for (int k = 0; k < KV; ++k)
+                if (owner[k])
+                    vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), prev[k]);
+        }
     }
     // merge into the running totals, or leave partials per group
-    if (!owner) return;
-    const long long base = owned_global(g, own_e);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
+    for (int k = 0; k < KV; ++k) {
+        if (!owner[k]) continue;
+        const long long base = owned_global(g, own_e[k]);
 #pragma unroll
-        for (int c = 0; c < G; ++c) {
-            const long long gi = (long long)s * n2 + base + c;
-            if (a.groups == 1) {
-                const double na = (double)a.done, nb = (double)count, nt = na + nb;
-                const double delta = (double)mean[s][c] - a.M[gi];
-                a.M[gi] += delta * (nb / nt);
-                a.M2[gi] += (double)m2[s][c] + delta * delta * (na * nb / nt);
-            } else {
-                AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
-                pp[base + c] = mean[s][c];
-                pp[n2 + base + c] = m2[s][c];
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const long long gi = (long long)s * n2 + base + c;
+                if (a.groups == 1) {
+                    const double na = (double)a.done, nb = (double)count, nt = na + nb;
+                    const double delta = (double)mean[s][k][c] - a.M[gi];
+                    a.M[gi] += delta * (nb / nt);
+                    a.M2[gi] += (double)m2[s][k][c] + delta * delta * (na * nb / nt);
+                } else {
+                    AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
+                    pp[base + c] = mean[s][k][c];
+                    pp[n2 + base + c] = m2[s][k][c];
+                }
             }
         }
     }
@@ -594,10 +632,14 @@ static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, i
             if (r > kMaxHaloRatio && !(ns == 1 && r <= 2 * kMaxHaloRatio)) continue;
             int nt = tw * th / (G * kVecPerThread);
             nt = nt < 256 ? 256 : (nt > 512 ? 512 : nt);
-            if (tw * th > nt * G * kVecPerThread) continue;
+            if (!noise && tw * th > nt * G * kVecPerThread) continue;  // write kernel: 2 vectors per thread
             if (noise) {
-                if ((TXT / G) * TVT > nt * kPrefetch) continue;  // prefetch registers
-                if (tw * th > (sizeof(T) == 8 ? 512 : 1024) * G) continue;  // one vector per thread
+                const int vec = tw * th / G;
+                if (vec > 2048) continue;  // owned vectors of at most 512 threads x 4
+                const NoiseCfg cfg = noise_cfg(vec);
+                if (sizeof(T) == 8 && cfg.nt > 512) continue;  // no 1024-thread double stages
+                if (cfg.kv > 1 && ns == 3) continue;  // three scales of state for 4 vectors would spill
+                if ((TXT / G) * TVT > cfg.nt * noise_prefetch(cfg.nt, cfg.kv)) continue;
             }
             // insertion by (overhead, LDS)
             int k = m++;
@@ -670,21 +712,21 @@ static hipError_t launch_stage(const StageArgs<T>& a, const StageGeom& g, int ma
     }
 }
 
-template <typename T, int NT, int NS>
+template <typename T, int NT, int NS, int KV>
 static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
                                         hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    {  // the tile must fit the prefetch registers and the owned vectors the threads
+    {  // the tile must fit the prefetch registers and the owned vectors of the threads
         constexpr int G = Vec<T>::G;
         const int d0 = 1 << (a.j0 - 1);
-        const int TXT = g.tw + 2 * stage_hx(d0, a.ns, G), TVT = g.th + 2 * 2 * ((1 << a.ns) - 1);
-        if ((TXT / G) * TVT > NT * noise_prefetch(NT) || g.tw * g.th > NT * G)
+        const int TXT = g.tw + 2 * stage_hx(d0, NS, G), TVT = g.th + 2 * 2 * ((1 << NS) - 1);
+        if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV) || g.tw * g.th > NT * KV * G)
             return hipErrorInvalidConfiguration;
     }
     static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
@@ -692,25 +734,23 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                     "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
                                     "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
     AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
-                k_starlet_noise_stage<T, NT, NS><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+                k_starlet_noise_stage<T, NT, NS, KV><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
     return hipGetLastError();
-}
-
-// Noise stages run one owned vector per thread: twice the write kernel's
-// threads per tile, at most 1024.
-static int noise_threads(const StageGeom& g, int G) {
-    int nt = g.tw * g.th / G;
-    return nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
 }
 
 template <typename T, int NS>
 static hipError_t launch_noise_stage_ns(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
                                         hipStream_t s) {
-    switch (noise_threads(g, Vec<T>::G)) {
-        case 256: return launch_noise_stage_nt<T, 256, NS>(a, g, tiles, s);
-        case 512: return launch_noise_stage_nt<T, 512, NS>(a, g, tiles, s);
-        case 1024:  // double-precision tiles hold at most 512 vectors
-            if constexpr (sizeof(T) == 4) return launch_noise_stage_nt<T, 1024, NS>(a, g, tiles, s);
+    const NoiseCfg cfg = noise_cfg(g.tw * g.th / Vec<T>::G);
+    if (cfg.kv == 4) {
+        if constexpr (NS < 3) return launch_noise_stage_nt<T, 512, NS, 4>(a, g, tiles, s);
+        return hipErrorInvalidConfiguration;
+    }
+    switch (cfg.nt) {
+        case 256: return launch_noise_stage_nt<T, 256, NS, 1>(a, g, tiles, s);
+        case 512: return launch_noise_stage_nt<T, 512, NS, 1>(a, g, tiles, s);
+        case 1024:  // double-precision tiles of 1024 vectors run 512 threads x 4 instead
+            if constexpr (sizeof(T) == 4) return launch_noise_stage_nt<T, 1024, NS, 1>(a, g, tiles, s);
             return hipErrorInvalidConfiguration;
         default: return hipErrorInvalidValue;
     }
@@ -861,6 +901,12 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
             s.part = a.part;
             s.inv_tvec = 1.0f / (float)((st.g.tw + 2 * stage_hx(d0, st.ns, Vec<T>::G)) / Vec<T>::G);
+            {
+                using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+                if (s.groups > 1 && (size_t)s.groups * st.ns * 2 * (size_t)n2 * sizeof(AccT) >
+                                        starlet_partials_bytes(a.logn, a.batch))
+                    return hipErrorInvalidConfiguration;
+            }
             e = launch_noise_stage<T>(s, st.g, tiles, a.stream);
             if (e == hipSuccess && s.groups > 1) {
                 using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
@@ -906,6 +952,12 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
 // Groups x scales x (mean, M2) x pixels in the accumulator type, bounded by
 // 256 groups of the largest tile (4096 pixels) and by one group per
 // realisation.
+// Partials of a multi-group noise stage: groups x ns x 2 planes of the
+// accumulator type, groups <= min(batch, 256 / tiles).  Three-scale stages
+// use tiles of at most 4096 pixels, so groups x n^2 <= 256 x 4096 and the
+// bound below is 3 x 2 x 8 bytes per such pixel; two-scale float stages may
+// use 8192-pixel tiles, needing 2 x 2 x 4 bytes per pixel of 256 x 8192,
+// which is less.  launch_starlet checks each stage against it.
 size_t starlet_partials_bytes(int logn, int batch) {
     const long long n2 = 1ll << (2 * logn);
     long long px = 256ll * 4096;
@@ -919,6 +971,15 @@ hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStrea
     AMAP_LAUNCH("reconstruct", s,
                 k_reconstruct<T><<<(unsigned)((n2 + 255) / 256), 256, 0, s>>>(planes, out, logn, J));
     return hipGetLastError();
+}
+
+// AMAP_TUNE_LOG=1 in the environment prints every timed candidate.
+static bool tune_log() {
+    static const bool on = [] {
+        const char* v = std::getenv("AMAP_TUNE_LOG");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
 }
 
 template <typename T>
@@ -940,8 +1001,20 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
         best[j] = -1.f;
         for (int ns = 1; ns <= 3 && j + ns <= J && e == hipSuccess; ++ns) {
             if (best[j + ns] < 0.f) continue;
-            StageGeom cand[4];
-            const int nc = stage_candidates<T>(n, j, ns, acc, cand, 4);
+            // the two best tiles (least halo overhead) of each thread configuration
+            StageGeom all[48], cand[16];
+            const int na = stage_candidates<T>(n, j, ns, acc, all, 48);
+            int nc = 0;
+            for (int i = 0; i < na && nc < 16; ++i) {
+                const int vec = all[i].tw * all[i].th / Vec<T>::G;
+                const int key = acc ? noise_cfg(vec).nt * 8 + noise_cfg(vec).kv : all[i].nt;
+                int same = 0;
+                for (int q = 0; q < nc; ++q) {
+                    const int vq = cand[q].tw * cand[q].th / Vec<T>::G;
+                    same += (acc ? noise_cfg(vq).nt * 8 + noise_cfg(vq).kv : cand[q].nt) == key;
+                }
+                if (same < 2) cand[nc++] = all[i];
+            }
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 StagePlan sub;
                 sub.nstages = 1;
@@ -960,6 +1033,10 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
                 float ms = 0.f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e != hipSuccess) break;
+                if (tune_log())
+                    std::fprintf(stderr, "amap tune: n=%d J=%d %s batch=%d stage j0=%d ns=%d tile %dx%d: %.1f us\n",
+                                 n, J, acc ? "noise" : "signal", a.batch, j, ns, cand[c].tw,
+                                 cand[c].th, 1e3f * ms / reps);
                 const float t = ms / reps + best[j + ns];
                 if (best[j] < 0.f || t < best[j]) {
                     best[j] = t;
