@@ -45,4 +45,6 @@ from .rng import (  # noqa: F401
 )
 from .noise import noise_sigma, snr_planes, rotate_shear  # noqa: F401
 from .peaks import count_peaks, count_peaks_planes  # noqa: F401
+from .stats import (peak_histogram, peak_histogram_planes, plane_moments,  # noqa: F401
+                    plane_moments_stack)
 from .pipeline import run_path  # noqa: F401
