@@ -15,6 +15,7 @@ Printed as one JSON line.  Extra objects:
                plan, and the same maps one launch sequence per map
   served       a Poisson request stream through the library's request loop:
                saturated rate, then p50/p99 latency at 0.5 and 0.8 of it
+  statistics   plane moments and peak-height histograms on the step's planes
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -414,6 +415,26 @@ def main():
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
+    # statistics of the step's planes: central moments of the J planes and
+    # the peak-height histogram of the S/N planes, 20 calls each
+    mom = torch.empty((J, 4), dtype=torch.float64, device=dev)
+    hist = torch.empty((J - 1, 40), dtype=torch.int64, device=dev)
+    stats = {}
+    for name, fn, nbytes in (
+            ("plane_moments", lambda: ctx.plane_moments(out["planes"], out=mom), 4.0 * J * N * N),
+            ("peak_histogram", lambda: ctx.peak_histogram(out["snr"], -2.0, 8.0, 40, 1, hist=hist),
+             4.0 * (J - 1) * N * N)):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(20):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) / 20 * 1e3
+        stats[name] = {"us_per_call": us, "alg_bytes": nbytes, "alg_GBps": nbytes / us / 1e3,
+                       "hbm_alg_frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+
     batched = served = None
     if not args.no_batched:
         print("bench: uneven batch", file=sys.stderr, flush=True)
@@ -433,7 +454,8 @@ def main():
         "wall_s_timed": wall,
         "hbm_alg_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
                         / (HBM_PEAK_GBS * 1e9),
-        "plain": plain, "batched": batched, "served": served, "roofline": roofline,
+        "plain": plain, "batched": batched, "served": served, "statistics": stats,
+        "roofline": roofline,
         "kernels": kernels,
     }
     ctx.close()

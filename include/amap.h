@@ -99,6 +99,13 @@ size_t amap_workspace_bytes(amap_ctx_t ctx);
  * unused until it is enabled again. */
 amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
 
+/* Writes the context's tuned schedules as JSON into buf (len bytes including
+ * the NUL): [{"elem": bytes per value, "logn", "J", "noise": 0|1, "batch",
+ * "stages": [[j0, ns, tile width, tile sub-rows], ...]}, ...]; an empty
+ * stage list means the analytic planner is used for that shape.
+ * AMAP_E_INVAL if it does not fit. */
+amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);
+
 /* Per-kernel timing (diagnostics): while enabled, every kernel the context
  * launches is bracketed by two HIP events recorded on the launch's stream.
  * Work captured into a batch plan's graph is not timed. */
@@ -211,6 +218,37 @@ amap_status amap_run_path(amap_ctx_t ctx, amap_dtype dt, int n, int J,
                           double threshold, void* kappa_e, void* kappa_b,
                           void* planes, void* sigma, void* snr,
                           long long* peaks, void* stream);
+
+/* ---- statistics of the planes ---- */
+
+/*
+ * Central moments of each of `nplanes` n x n planes (Sec. 2.2: the variance
+ * of the aperture mass, eq:varmap, its skewness and its kurtosis are the
+ * statistics drawn from M_ap maps; plane w_j is the M_ap map at theta = 2^j).
+ * out (device, 8-byte aligned, 4*nplanes doubles) receives, per plane p,
+ * out[4p] = mean and out[4p+k-1] = m_k = (1/n^2) sum (x - mean)^k for
+ * k = 2, 3, 4: the variance is m2, the skewness m3 / m2^1.5, the excess
+ * kurtosis m4 / m2^2 - 3.  Two passes over the planes (mean, then the
+ * central sums), accumulated in double with a fixed reduction order, so
+ * results are reproducible.  Uses the context workspace.
+ */
+amap_status amap_plane_moments(amap_ctx_t ctx, amap_dtype dt, int n, int nplanes,
+                               const void* planes, double* out, void* stream);
+
+/*
+ * Histogram of peak heights on each plane (Sec. 2.2: peak counts of M_ap
+ * maps; richer peak statistics than amap_count_peaks).  A pixel counts when
+ * sign*value exceeds sign*value of all 8 periodic neighbours, strictly
+ * (sign = +1: peaks; sign = -1: troughs, i.e. peaks of the negated plane);
+ * its height h = sign*value goes to bin floor((h - lo) / ((hi - lo) / nbins)),
+ * computed in double, when that bin is in [0, nbins).  NaN is never a peak.
+ * hist: device, 8-byte aligned, nplanes*nbins long long, overwritten.
+ * 1 <= nbins <= 16384; lo < hi finite.  Counts above thresholds t_k follow
+ * by summing bins.
+ */
+amap_status amap_peak_histogram(amap_ctx_t ctx, amap_dtype dt, int n, int nplanes,
+                                const void* planes, int sign, double lo, double hi, int nbins,
+                                long long* hist, void* stream);
 
 /* ---- batched maps: one launch sequence over many maps of uneven sizes ---- */
 

@@ -80,6 +80,8 @@ def load():
         "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
         "amap_count_peaks": (I, [P, I, I, I, P, D, P, P]),
         "amap_phase_uniforms": (I, [P, I, U64, U64, P, P]),
+        "amap_peak_histogram": (I, [P, I, I, I, P, I, D, D, I, P, P]),
+        "amap_plane_moments": (I, [P, I, I, I, P, P, P]),
         "amap_run_path": (I, [P, I, I, I, P, P, I, U64, D, P, P, P, P, P, P, P]),
         "amap_batch_plan": (I, [P, I, ctypes.POINTER(AmapJob), I, ctypes.POINTER(P)]),
         "amap_batch_run": (I, [P, P]),
@@ -242,6 +244,24 @@ class Context:
         _check(load().amap_count_peaks(self._h, _dt(snr), n, nplanes, _ptr(snr), float(threshold),
                                        _ptr(counts), _stream()))
         return counts
+
+    def peak_histogram(self, planes, lo, hi, nbins, sign=1, hist=None):
+        """Binned peak (sign=+1) or trough (sign=-1) heights per plane."""
+        nplanes, n = planes.shape[0], _side(planes)
+        hist = (torch.empty((nplanes, nbins), dtype=torch.int64, device=planes.device)
+                if hist is None else hist)
+        _check(load().amap_peak_histogram(self._h, _dt(planes), n, nplanes, _ptr(planes), int(sign),
+                                          float(lo), float(hi), int(nbins), _ptr(hist), _stream()))
+        return hist
+
+    def plane_moments(self, planes, out=None):
+        """Per plane [mean, m2, m3, m4] (float64, on the device)."""
+        nplanes, n = planes.shape[0], _side(planes)
+        out = (torch.empty((nplanes, 4), dtype=torch.float64, device=planes.device)
+               if out is None else out)
+        _check(load().amap_plane_moments(self._h, _dt(planes), n, nplanes, _ptr(planes), _ptr(out),
+                                         _stream()))
+        return out
 
     def phase_uniforms(self, n, seed, r, out=None):
         out = torch.empty((n, n), dtype=torch.int32, device=self.device) if out is None else out

@@ -100,6 +100,14 @@ template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
 // True when every stage of an n x n, J-plane transform has an LDS tile
 // (grouped maps need it).
 template <typename T> bool starlet_all_tiled(int n, int J);
+template <typename T>
+hipError_t launch_peak_hist(int logn, int nplanes, const T* planes, int sign, double lo,
+                            double width, int nbins, long long* hist, hipStream_t s);
+// Blocks per plane of the moment reductions (their partials: 3 x nplanes x this doubles).
+int moment_blocks(int logn);
+template <typename T>
+hipError_t launch_plane_moments(int logn, int nplanes, const T* planes, double* part, double* out4,
+                                hipStream_t s);
 // Times candidate tiles of every stage start and scale count on a's buffers
 // (reps launches each, on a.stream, synchronously) and picks the schedule of
 // least total time by dynamic programming over the stage starts.  Writes

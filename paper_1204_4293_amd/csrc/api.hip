@@ -737,6 +737,58 @@ amap_status amap_count_peaks(amap_ctx_t c, amap_dtype dt, int n, int nplanes, co
     return AMAP_OK;
 }
 
+amap_status amap_peak_histogram(amap_ctx_t c, amap_dtype dt, int n, int nplanes, const void* planes,
+                                int sign, double lo, double hi, int nbins, long long* hist,
+                                void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    if (nplanes < 1 || nplanes > 65535) return fail(AMAP_E_INVAL, "nplanes must be in [1, 65535]");
+    AMAP_TRY(check_ptr(planes, "planes"));
+    if (!hist || reinterpret_cast<uintptr_t>(hist) % 8 != 0)
+        return fail(AMAP_E_INVAL, "hist must be a non-NULL 8-byte aligned device pointer");
+    if (sign != 1 && sign != -1) return fail(AMAP_E_INVAL, "sign must be +1 or -1 (got %d)", sign);
+    if (nbins < 1 || nbins > 16384) return fail(AMAP_E_INVAL, "nbins must be in [1, 16384]");
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+        return fail(AMAP_E_INVAL, "need finite lo < hi");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    const double width = (hi - lo) / (double)nbins;
+    hipError_t e = dt == AMAP_F32
+        ? launch_peak_hist<float>(logn, nplanes, (const float*)planes, sign, lo, width, nbins, hist, s)
+        : launch_peak_hist<double>(logn, nplanes, (const double*)planes, sign, lo, width, nbins, hist, s);
+    if (e != hipSuccess) return hip_fail(e, "peak histogram kernel");
+    return AMAP_OK;
+}
+
+amap_status amap_plane_moments(amap_ctx_t c, amap_dtype dt, int n, int nplanes, const void* planes,
+                               double* out, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    if (nplanes < 1 || nplanes > 65535) return fail(AMAP_E_INVAL, "nplanes must be in [1, 65535]");
+    AMAP_TRY(check_ptr(planes, "planes"));
+    if (!out || reinterpret_cast<uintptr_t>(out) % 8 != 0)
+        return fail(AMAP_E_INVAL, "out must be a non-NULL 8-byte aligned device pointer");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    const int logn = ilog2(n);
+    AMAP_TRY(c->ws.reserve((size_t)3 * nplanes * moment_blocks(logn) * sizeof(double)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* part = static_cast<double*>(c->ws.ptr);
+    hipError_t e = dt == AMAP_F32
+        ? launch_plane_moments<float>(logn, nplanes, (const float*)planes, part, out, s)
+        : launch_plane_moments<double>(logn, nplanes, (const double*)planes, part, out, s);
+    if (e != hipSuccess) return hip_fail(e, "moment kernels");
+    return AMAP_OK;
+}
+
 amap_status amap_phase_uniforms(amap_ctx_t c, int n, uint64_t seed, uint64_t r, uint32_t* out_u32,
                                 void* stream) {
     g_last_error.clear();

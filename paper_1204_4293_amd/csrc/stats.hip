@@ -62,6 +62,116 @@ k_count_peaks(const T* __restrict__ snr, int logn, double thr, long long* __rest
         atomicAdd((unsigned long long*)&counts[blockIdx.y], (unsigned long long)__popcll(mask));
 }
 
+// Histogram of peak heights (Sec. 2.2): pixels that are strict 8-neighbour
+// maxima of sign*value, periodic, binned by h = sign*value into nbins equal
+// bins over [lo, lo + nbins*width); the bin is floor((h - lo) / width) in
+// double.  Counts gather in LDS and are added to hist once per block.
+// grid (n*n/256, nplanes).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_peak_hist(const T* __restrict__ planes, int logn, int sign, double lo, double width, int nbins,
+            long long* __restrict__ hist) {
+    extern __shared__ unsigned int bins[];
+    for (int b = threadIdx.x; b < nbins; b += 256) bins[b] = 0u;
+    __syncthreads();
+    const int n = 1 << logn, m = n - 1;
+    const long long n2 = (long long)n * n;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n2) {
+        const T* p = planes + (long long)blockIdx.y * n2;
+        const int x = (int)(idx & m), y = (int)(idx >> logn);
+        const T h = sign > 0 ? p[idx] : -p[idx];
+        bool peak = true;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const long long row = (long long)((y + dy) & m) * n;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                const T q = p[row + ((x + dx) & m)];
+                peak = peak && (h > (sign > 0 ? q : -q));
+            }
+        }
+        if (peak) {
+            const double b = floor(((double)h - lo) / width);
+            if (b >= 0.0 && b < (double)nbins) atomicAdd(&bins[(int)b], 1u);
+        }
+    }
+    __syncthreads();
+    long long* out = hist + (long long)blockIdx.y * nbins;
+    for (int b = threadIdx.x; b < nbins; b += 256)
+        if (bins[b]) atomicAdd((unsigned long long*)&out[b], (unsigned long long)bins[b]);
+}
+
+// ---- plane moments: deterministic two-pass reductions in double -----------------
+// Sum of a block's 256 values (fixed order: wave shuffles, then the waves).
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return t;
+}
+
+// Pass 1: per-block sums of a plane (grid (nb, nplanes)); pass 2 (mean
+// given): per-block sums of (x - mean)^k, k = 2, 3, 4.  part is
+// [3][nplanes][nb].
+template <typename T, bool CENTRAL>
+__global__ void __launch_bounds__(256)
+k_moment_part(const T* __restrict__ planes, long long n2, const double* __restrict__ out4,
+              double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int pl = blockIdx.y, nb = gridDim.x;
+    const T* p = planes + (long long)pl * n2;
+    const double mu = CENTRAL ? out4[4 * pl] : 0.0;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long long)nb * 256) {
+        const double d = (double)p[i] - mu;
+        if (CENTRAL) {
+            const double d2 = d * d;
+            s1 += d2;
+            s2 += d2 * d;
+            s3 += d2 * d2;
+        } else {
+            s1 += d;
+        }
+    }
+    const long long o = (long long)pl * nb + blockIdx.x;
+    const long long stride = (long long)gridDim.y * nb;
+    const double t1 = block_sum256(s1, sh);
+    if (!CENTRAL) {
+        if (threadIdx.x == 0) part[o] = t1;
+        return;
+    }
+    const double t2 = block_sum256(s2, sh);
+    const double t3 = block_sum256(s3, sh);
+    if (threadIdx.x == 0) {
+        part[o] = t1;
+        part[stride + o] = t2;
+        part[2 * stride + o] = t3;
+    }
+}
+
+// Folds the nb partials of each plane (one block per plane, fixed order):
+// the mean (pass 1) or m2, m3, m4 (pass 2) into out4[4 * plane + ...].
+template <bool CENTRAL>
+__global__ void __launch_bounds__(256)
+k_moment_fold(const double* __restrict__ part, int nb, long long n2, double* __restrict__ out4) {
+    __shared__ double sh[4];
+    const int pl = blockIdx.x, np = gridDim.x;
+    const long long stride = (long long)np * nb;
+    const int K = CENTRAL ? 3 : 1;
+    for (int k = 0; k < K; ++k) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) v += part[k * stride + (long long)pl * nb + b];
+        const double t = block_sum256(v, sh);
+        if (threadIdx.x == 0) out4[4 * pl + (CENTRAL ? 1 + k : 0)] = t / (double)n2;
+    }
+}
+
 // Thread t writes the eight 32-bit values of Philox block t.
 __global__ void __launch_bounds__(256)
 k_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* __restrict__ out) {
@@ -107,6 +217,38 @@ hipError_t launch_count_peaks(int logn, int nplanes, const T* snr, double thr, l
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_peak_hist(int logn, int nplanes, const T* planes, int sign, double lo,
+                            double width, int nbins, long long* hist, hipStream_t s) {
+    const long long n2 = 1ll << (2 * logn);
+    hipError_t e = launch_zero_i64(hist, (long long)nplanes * nbins, s);
+    if (e != hipSuccess) return e;
+    AMAP_LAUNCH("peak_hist", s,
+                k_peak_hist<T><<<dim3(blocks_for(n2), nplanes), 256, nbins * sizeof(unsigned int), s>>>(
+                    planes, logn, sign, lo, width, nbins, hist));
+    return hipGetLastError();
+}
+
+int moment_blocks(int logn) {
+    const long long n2 = 1ll << (2 * logn);
+    long long nb = n2 / (256 * 8);  // about eight values per thread
+    return (int)(nb < 1 ? 1 : (nb > 1024 ? 1024 : nb));
+}
+
+template <typename T>
+hipError_t launch_plane_moments(int logn, int nplanes, const T* planes, double* part, double* out4,
+                                hipStream_t s) {
+    const long long n2 = 1ll << (2 * logn);
+    const int nb = moment_blocks(logn);
+    AMAP_LAUNCH("moments_mean", s,
+                k_moment_part<T, false><<<dim3(nb, nplanes), 256, 0, s>>>(planes, n2, out4, part));
+    AMAP_LAUNCH("moments_fold", s, k_moment_fold<false><<<nplanes, 256, 0, s>>>(part, nb, n2, out4));
+    AMAP_LAUNCH("moments_central", s,
+                k_moment_part<T, true><<<dim3(nb, nplanes), 256, 0, s>>>(planes, n2, out4, part));
+    AMAP_LAUNCH("moments_fold", s, k_moment_fold<true><<<nplanes, 256, 0, s>>>(part, nb, n2, out4));
+    return hipGetLastError();
+}
+
 hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, hipStream_t s) {
     const long long n2 = 1ll << (2 * logn);
     AMAP_LAUNCH("phase_u32", s, k_phase_u32<<<blocks_for(n2 / 8), 256, 0, s>>>(logn, seed, r, out));
@@ -119,5 +261,11 @@ template hipError_t launch_noise_finalize<double>(int, int, int, const double*, 
                                                   double*, double*, hipStream_t);
 template hipError_t launch_count_peaks<float>(int, int, const float*, double, long long*, hipStream_t);
 template hipError_t launch_count_peaks<double>(int, int, const double*, double, long long*, hipStream_t);
+template hipError_t launch_peak_hist<float>(int, int, const float*, int, double, double, int, long long*,
+                                            hipStream_t);
+template hipError_t launch_peak_hist<double>(int, int, const double*, int, double, double, int,
+                                             long long*, hipStream_t);
+template hipError_t launch_plane_moments<float>(int, int, const float*, double*, double*, hipStream_t);
+template hipError_t launch_plane_moments<double>(int, int, const double*, double*, double*, hipStream_t);
 
 }  // namespace amap
