@@ -16,6 +16,8 @@ Printed as one JSON line.  Extra objects:
   served       a Poisson request stream through the library's request loop:
                saturated rate, then p50/p99 latency at 0.5 and 0.8 of it
   statistics   plane moments and peak-height histograms on the step's planes
+  direct_vs_starlet  map_direct at theta = 2..64 (cut theta) vs KS + starlet
+               with J = log2 theta + 1 on the 1024^2 map (the paper's comparison)
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -415,6 +417,34 @@ def main():
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
 
+    # direct aperture mass vs the starlet on the 1024^2 map: map_direct at
+    # theta = 2..64 px with the starlet filter truncated at cut = theta, vs
+    # KS + starlet with J = log2(theta) + 1 planes (all scales up to theta)
+    direct = {}
+    for theta in (2, 4, 8, 16, 32, 64):
+        Jt = theta.bit_length()
+        dm = torch.empty((N, N), dtype=torch.float32, device=dev)
+        pt = torch.empty((Jt, N, N), dtype=torch.float32, device=dev)
+        ctx.map_direct(t1, t2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=dm)
+        ctx.starlet_forward(ctx.ks_invert(t1, t2, kappa_e=ke)[0], Jt, planes=pt)
+        torch.cuda.synchronize()
+        reps = 5 if theta >= 32 else 20
+        ev0.record()
+        for _ in range(reps):
+            ctx.map_direct(t1, t2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=dm)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_dir = ev0.elapsed_time(ev1) / reps
+        ev0.record()
+        for _ in range(20):
+            ctx.ks_invert(t1, t2, kappa_e=ke)
+            ctx.starlet_forward(ke, Jt, planes=pt)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_sw = ev0.elapsed_time(ev1) / 20
+        direct["theta_%d" % theta] = {"J": Jt, "map_direct_ms": t_dir, "ks_starlet_ms": t_sw,
+                                      "speedup": t_dir / t_sw}
+
     # statistics of the step's planes: central moments of the J planes and
     # the peak-height histogram of the S/N planes, 20 calls each
     mom = torch.empty((J, 4), dtype=torch.float64, device=dev)
@@ -455,6 +485,7 @@ def main():
         "hbm_alg_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
                         / (HBM_PEAK_GBS * 1e9),
         "plain": plain, "batched": batched, "served": served, "statistics": stats,
+        "direct_vs_starlet": direct,
         "roofline": roofline,
         "kernels": kernels,
     }
