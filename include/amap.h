@@ -101,7 +101,8 @@ amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
 
 /* Writes the context's tuned schedules as JSON into buf (len bytes including
  * the NUL): [{"elem": bytes per value, "logn", "J", "noise": 0|1, "batch",
- * "stages": [[j0, ns, tile width, tile sub-rows], ...]}, ...]; an empty
+ * "stages": [[j0, ns, tile width, tile sub-rows, realisations per LDS
+ * pass], ...]}, ...]; an empty
  * stage list means the analytic planner is used for that shape.
  * AMAP_E_INVAL if it does not fit. */
 amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);

@@ -65,11 +65,11 @@ template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 // Scratch (each batch*n*n): cbuf0 (always), cbuf1 (ACC), tmp; wbuf (ACC):
 // 3*batch*n*n, the detail planes of one stage.
 // A starlet stage schedule: stage k covers scales st[k].j0 .. j0+ns-1 with
-// an LDS tile of tw pixels by th sub-rows.  nstages == 0: use the analytic
-// planner.
+// an LDS tile of tw pixels by th sub-rows, rb realisations per LDS pass
+// (noise stages; 1 otherwise).  nstages == 0: use the analytic planner.
 struct StagePlan {
     int nstages = 0;
-    struct Stage { int j0, ns, tw, th; } st[16];
+    struct Stage { int j0, ns, tw, th, rb; } st[16];
 };
 
 template <typename T>

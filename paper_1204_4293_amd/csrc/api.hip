@@ -473,7 +473,7 @@ amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
         out += item;
         for (int k = 0; k < kv.second.nstages; ++k) {
             const StagePlan::Stage& t = kv.second.st[k];
-            snprintf(item, sizeof item, "%s[%d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th);
+            snprintf(item, sizeof item, "%s[%d, %d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th, t.rb);
             out += item;
         }
         out += "]}";

@@ -123,11 +123,12 @@ __host__ __device__ constexpr NoiseCfg noise_cfg(int vec) {
          : vec <= 1024 ? NoiseCfg{1024, 1}
          : NoiseCfg{512, 4};
 }
-// Prefetch registers (16-byte vectors) per thread: a tile's vectors may not
-// exceed nt times this.  One-vector stages keep 3 (their 128-register
-// budget); four-vector stages hold 8.
-__host__ __device__ constexpr int noise_prefetch(int nt, int kv) {
-    return kv > 1 ? 8 : 3;
+// Prefetch registers (16-byte vectors) per thread and realisation: a tile's
+// vectors may not exceed nt times this.  One-vector stages keep 3 (their
+// 128-register budget), or 2 when two realisations are processed at a time;
+// four-vector stages hold 8.
+__host__ __device__ constexpr int noise_prefetch(int nt, int kv, int rb = 1) {
+    return kv > 1 ? 8 : (rb > 1 ? 2 : 3);
 }
 
 // Barrier that orders only LDS accesses, so global loads issued before it
@@ -185,9 +186,9 @@ __device__ __forceinline__ int fdiv(int e, float inv_d) {
 // [xlo, xhi) x [vlo, vhi), which the call updates.  Work items are (row,
 // vector) pairs spread over all threads; each thread takes two row items at
 // a time so their LDS reads overlap.
-template <typename T, int NT>
+template <typename T, int NT, int RB = 1>
 __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, int s, int& xlo,
-                                                int& xhi, int& vlo, int& vhi) {
+                                                int& xhi, int& vlo, int& vhi, int tstride = 0) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
     const int tid = threadIdx.x;
@@ -200,18 +201,21 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
     const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
     const float inv_nv = 1.0f / (float)nv;
     const int rtot = nv * (vhi - vlo);
-    for (int e0 = tid; e0 < rtot; e0 += 2 * NT) {
+    // RB tiles share each pass: item e of tile t is e + t * rtot
+    for (int e0 = tid; e0 < RB * rtot; e0 += 2 * NT) {
         VA o[2];
         int off[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int e = e0 + u * NT;
+            int e = e0 + u * NT;
             off[u] = -1;
-            if (e < rtot) {
+            if (e < RB * rtot) {
+                int tb = 0;
+                if (RB > 1 && e >= rtot) { e -= rtot; tb = tstride; }
                 const int r = fdiv(e, inv_nv);
                 const int i0 = rlo4 + (e - r * nv) * G;
-                const T* ra = A + (vlo + r) * RS;
-                off[u] = (vlo + r) * RS + i0;
+                const T* ra = A + tb + (vlo + r) * RS;
+                off[u] = tb + (vlo + r) * RS + i0;
                 if (2 * dx <= G) {  // the five taps of all G outputs lie in three vectors
                     const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
                              rr = vload<T, G>(ra + i0 + G);
@@ -244,13 +248,15 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
     const int lmax = (chi - clo + dv - 1) / dv;
     const int nseg = (lmax + kSegLen - 1) / kSegLen;
     const int items = nv * dv * nseg;
-    for (int it = tid; it < items; it += NT) {
+    for (int it0 = tid; it0 < RB * items; it0 += NT) {
+        int it = it0, tb = 0;
+        if (RB > 1 && it >= items) { it -= items; tb = tstride; }
         const int r = fdiv(it, inv_nv);
         const int i0 = rlo4 + (it - r * nv) * G;
         const int phase = r & (dv - 1), seg = r >> s;
         const int vfirst = clo + phase + dv * (seg * kSegLen);
         if (vfirst >= chi) continue;
-        const T* col = Bf + i0;
+        const T* col = Bf + tb + i0;
         VA win[kSegLen + 4];
 #pragma unroll
         for (int k = 0; k < kSegLen + 4; ++k) {
@@ -261,7 +267,7 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
         for (int k = 0; k < kSegLen; ++k) {
             const int v = vfirst + dv * k;
             if (v < chi)
-                vstore<T, G>(A + v * RS + i0,
+                vstore<T, G>(A + tb + v * RS + i0,
                              vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
         }
     }
@@ -376,7 +382,7 @@ struct NoiseStageArgs {
 // Single-precision one-vector stages of 256 or 512 threads keep to 128
 // registers, so that two or more workgroups share a CU and overlap each
 // other's barrier phases.
-template <typename T, int NT, int NS, int KV>
+template <typename T, int NT, int NS, int KV, int RB>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && KV == 1 && NT <= 512) ? 4 : 1)
 k_starlet_noise_stage(NoiseStageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
@@ -385,15 +391,18 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
     using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
     const TileGeom g = tile_geom(a.logn, a.j0, NS, a.log_tw, a.th, G);
     const long long n2 = (long long)g.n * g.n;
+    // RB realisations at a time, tile t in [A_t | B_t], A_t = A + t * tstride
+    const int tstride = 2 * g.RS * g.TVT;
     T* A = reinterpret_cast<T*>(smem_raw) + G;
     T* Bf = A + g.RS * g.TVT;
     const int grp = blockIdx.y;
     const int count = (a.batch - grp + a.groups - 1) / a.groups;
+    const int rounds = (count + RB - 1) / RB;
     const int tvec = g.TXT / G;
     const int nload = tvec * g.TVT;
 
-    constexpr int PF = noise_prefetch(NT, KV);
-    VA pf[PF];
+    constexpr int PF = noise_prefetch(NT, KV, RB);
+    VA pf[RB][PF];
     AccT mean[NS][KV][G], m2[NS][KV][G];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -409,70 +418,81 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
         owner[k] = (int)threadIdx.x + k * NT < g.nvec;
         own_e[k] = ((int)threadIdx.x + k * NT) * G;
     }
+    // tile of the i-th realisation of this group into prefetch slot t
+    auto fetch = [&](int i, int t) {
+        const T* src = a.src + (long long)(grp + i * a.groups) * n2;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if (e < nload) {
+                const int v = fdiv(e, a.inv_tvec);
+                pf[t][k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + (e - v * tvec) * G) & g.m));
+            }
+        }
+    };
 
-    // first tile
-    if (count > 0) {
-        const T* src = a.src + (long long)grp * n2;
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int e = threadIdx.x + k * NT;
-            if (e < nload) {
-                const int v = fdiv(e, a.inv_tvec);
-                pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + (e - v * tvec) * G) & g.m));
-            }
-        }
-    }
-    for (int it = 0; it < count; ++it) {
-        const int b = grp + it * a.groups;
-        lds_barrier();  // the previous realisation is done with A and B
+    for (int t = 0; t < RB; ++t)
+        if (t < count) fetch(t, t);
+    for (int ro = 0; ro < rounds; ++ro) {
+        const int i0 = ro * RB;  // first realisation index of the round
+        lds_barrier();  // the previous round is done with the tiles
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int e = threadIdx.x + k * NT;
-            if (e < nload) {
-                const int v = fdiv(e, a.inv_tvec);
-                vstore<T, G>(A + v * g.RS + (e - v * tvec) * G, pf[k]);
-            }
-        }
-        if (it + 1 < count) {  // prefetch the next realisation's tile
-            const T* src = a.src + (long long)(b + a.groups) * n2;
+        for (int t = 0; t < RB; ++t) {
+            if (i0 + t >= count) continue;
 #pragma unroll
             for (int k = 0; k < PF; ++k) {
                 const int e = threadIdx.x + k * NT;
                 if (e < nload) {
                     const int v = fdiv(e, a.inv_tvec);
-                    pf[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + (e - v * tvec) * G) & g.m));
+                    vstore<T, G>(A + t * tstride + v * g.RS + (e - v * tvec) * G, pf[t][k]);
                 }
             }
         }
-        lds_barrier();
-        VA prev[KV];
 #pragma unroll
-        for (int k = 0; k < KV; ++k)
-            if (owner[k]) prev[k] = vload<T, G>(A + owned_lds(g, own_e[k]));
-        const AccT inv = (AccT)1 / (AccT)(it + 1);
+        for (int t = 0; t < RB; ++t)  // prefetch the next round's tiles
+            if (i0 + RB + t < count) fetch(i0 + RB + t, t);
+        lds_barrier();
+        VA prev[RB][KV];
+#pragma unroll
+        for (int t = 0; t < RB; ++t)
+#pragma unroll
+            for (int k = 0; k < KV; ++k)
+                if (owner[k]) prev[t][k] = vload<T, G>(A + t * tstride + owned_lds(g, own_e[k]));
         int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
-            tile_scale_pass<T, NT>(A, Bf, g, s, xlo, xhi, vlo, vhi);
+            tile_scale_pass<T, NT, RB>(A, Bf, g, s, xlo, xhi, vlo, vhi, tstride);
+            // realisations in order, so the update sequence matches one at a time
 #pragma unroll
-            for (int k = 0; k < KV; ++k) {
-                if (!owner[k]) continue;
-                const VA c = vload<T, G>(A + owned_lds(g, own_e[k]));
+            for (int t = 0; t < RB; ++t) {
+                if (i0 + t >= count) continue;
+                const AccT inv = (AccT)1 / (AccT)(i0 + t + 1);
 #pragma unroll
-                for (int cc = 0; cc < G; ++cc) {
-                    const AccT x = (AccT)(prev[k].e[cc] - c.e[cc]);
-                    const AccT d = x - mean[s][k][cc];
-                    mean[s][k][cc] = fma(d, inv, mean[s][k][cc]);
-                    m2[s][k][cc] = fma(d, x - mean[s][k][cc], m2[s][k][cc]);
+                for (int k = 0; k < KV; ++k) {
+                    if (!owner[k]) continue;
+                    const VA c = vload<T, G>(A + t * tstride + owned_lds(g, own_e[k]));
+#pragma unroll
+                    for (int cc = 0; cc < G; ++cc) {
+                        const AccT x = (AccT)(prev[t][k].e[cc] - c.e[cc]);
+                        const AccT d = x - mean[s][k][cc];
+                        mean[s][k][cc] = fma(d, inv, mean[s][k][cc]);
+                        m2[s][k][cc] = fma(d, x - mean[s][k][cc], m2[s][k][cc]);
+                    }
+                    prev[t][k] = c;
                 }
-                prev[k] = c;
             }
         }
         if (a.cout) {
 #pragma unroll
-            for (int k = 0; k < KV; ++k)
-                if (owner[k])
-                    vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), prev[k]);
+            for (int t = 0; t < RB; ++t) {
+                if (i0 + t >= count) continue;
+                const int b = grp + (i0 + t) * a.groups;
+#pragma unroll
+                for (int k = 0; k < KV; ++k)
+                    if (owner[k])
+                        vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), prev[t][k]);
+            }
         }
     }
     // merge into the running totals, or leave partials per group
@@ -605,7 +625,11 @@ k_reconstruct(const T* __restrict__ planes, T* __restrict__ out, int logn, int J
 struct StageGeom {
     int ns, nt, tw, th;
     size_t lds;
+    int rb = 1;  // realisations per LDS pass (noise stages)
 };
+
+// Most tile candidates of one stage (tile widths x heights x pass widths).
+constexpr int kMaxCand = 64;
 
 // Largest tile overhead accepted for a stage (LDS elements per output pixel).
 constexpr double kMaxHaloRatio = 2.6;
@@ -613,15 +637,29 @@ constexpr double kMaxHaloRatio = 2.6;
 // Tiles for a stage of ns scales from j0 whose two LDS buffers fit and whose
 // halo overhead is bounded, best first (smallest overhead, then least LDS);
 // noise stages also need the tile to fit the prefetch registers and one
-// owned vector per thread.  Returns the number written to out (at most cap).
+// owned vector per thread.  Float noise stages of one or two scales with one
+// owned vector per thread are also offered with two realisations per LDS
+// pass (twice the LDS, fewer barriers per realisation).  Returns the number
+// written to out (at most cap).
 template <typename T>
 static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, int cap) {
     constexpr int G = Vec<T>::G;
     const int d0 = 1 << (j0 - 1);
     const int Hx = stage_hx(d0, ns, G), Hv = 2 * ((1 << ns) - 1);
-    StageGeom all[48];
-    double ratio[48];
+    StageGeom all[kMaxCand];
+    double ratio[kMaxCand];
     int m = 0;
+    auto insert = [&](const StageGeom& sg, double r) {  // by (overhead, LDS)
+        int k = m++;
+        while (k > 0 && (r < ratio[k - 1] - 1e-9 ||
+                         (r < ratio[k - 1] + 1e-9 && sg.lds < all[k - 1].lds))) {
+            all[k] = all[k - 1];
+            ratio[k] = ratio[k - 1];
+            --k;
+        }
+        all[k] = sg;
+        ratio[k] = r;
+    };
     for (int tw = 256; tw >= 16; tw /= 2) {
         for (int th = 64; th >= 2; th /= 2) {
             if (tw > n || th > n / d0) continue;
@@ -641,16 +679,14 @@ static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, i
                 if (cfg.kv > 1 && ns == 3) continue;  // three scales of state for 4 vectors would spill
                 if ((TXT / G) * TVT > cfg.nt * noise_prefetch(cfg.nt, cfg.kv)) continue;
             }
-            // insertion by (overhead, LDS)
-            int k = m++;
-            while (k > 0 && (r < ratio[k - 1] - 1e-9 ||
-                             (r < ratio[k - 1] + 1e-9 && lds < all[k - 1].lds))) {
-                all[k] = all[k - 1];
-                ratio[k] = ratio[k - 1];
-                --k;
+            insert(StageGeom{ns, nt, tw, th, lds, 1}, r);
+            if (noise && sizeof(T) == 4 && ns <= 2) {
+                const NoiseCfg cfg = noise_cfg(tw * th / G);
+                const size_t lds2 = 4 * (size_t)(TXT + 2 * G) * TVT * sizeof(T) + G * sizeof(T);
+                if (cfg.kv == 1 && lds2 <= (size_t)kLdsBytes &&
+                    (TXT / G) * TVT <= cfg.nt * noise_prefetch(cfg.nt, 1, 2))
+                    insert(StageGeom{ns, nt, tw, th, lds2, 2}, r);
             }
-            all[k] = StageGeom{ns, nt, tw, th, lds};
-            ratio[k] = r;
         }
     }
     const int c = m < cap ? m : cap;
@@ -670,11 +706,12 @@ static bool pick_stage(int n, int j0, int left, bool noise, StageGeom* g) {
 
 // The geometry of a given tile (as the planner would size it).
 template <typename T>
-static bool stage_geom_of(int n, int j0, int ns, int tw, int th, bool noise, StageGeom* g) {
-    StageGeom all[48];
-    const int m = stage_candidates<T>(n, j0, ns, noise, all, 48);
+static bool stage_geom_of(int n, int j0, int ns, int tw, int th, int rb, bool noise,
+                          StageGeom* g) {
+    StageGeom all[kMaxCand];
+    const int m = stage_candidates<T>(n, j0, ns, noise, all, kMaxCand);
     for (int i = 0; i < m; ++i)
-        if (all[i].tw == tw && all[i].th == th) {
+        if (all[i].tw == tw && all[i].th == th && all[i].rb == rb) {
             *g = all[i];
             return true;
         }
@@ -712,12 +749,12 @@ static hipError_t launch_stage(const StageArgs<T>& a, const StageGeom& g, int ma
     }
 }
 
-template <typename T, int NT, int NS, int KV>
+template <typename T, int NT, int NS, int KV, int RB>
 static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageGeom& g, int tiles,
                                         hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV, RB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -726,7 +763,8 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
         constexpr int G = Vec<T>::G;
         const int d0 = 1 << (a.j0 - 1);
         const int TXT = g.tw + 2 * stage_hx(d0, NS, G), TVT = g.th + 2 * 2 * ((1 << NS) - 1);
-        if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV) || g.tw * g.th > NT * KV * G)
+        if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV, RB) || g.tw * g.th > NT * KV * G ||
+            g.lds < (size_t)(2 * RB * (TXT + 2 * G) * TVT + G) * sizeof(T))
             return hipErrorInvalidConfiguration;
     }
     static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
@@ -734,7 +772,7 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                     "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
                                     "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
     AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
-                k_starlet_noise_stage<T, NT, NS, KV><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+                k_starlet_noise_stage<T, NT, NS, KV, RB><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
     return hipGetLastError();
 }
 
@@ -743,14 +781,28 @@ static hipError_t launch_noise_stage_ns(const NoiseStageArgs<T>& a, const StageG
                                         hipStream_t s) {
     const NoiseCfg cfg = noise_cfg(g.tw * g.th / Vec<T>::G);
     if (cfg.kv == 4) {
-        if constexpr (NS < 3) return launch_noise_stage_nt<T, 512, NS, 4>(a, g, tiles, s);
+        if constexpr (NS < 3) {
+            if (g.rb == 1) return launch_noise_stage_nt<T, 512, NS, 4, 1>(a, g, tiles, s);
+        }
         return hipErrorInvalidConfiguration;
     }
+    if (g.rb == 2) {  // float stages of one or two scales only
+        if constexpr (sizeof(T) == 4 && NS < 3) {
+            switch (cfg.nt) {
+                case 256: return launch_noise_stage_nt<T, 256, NS, 1, 2>(a, g, tiles, s);
+                case 512: return launch_noise_stage_nt<T, 512, NS, 1, 2>(a, g, tiles, s);
+                case 1024: return launch_noise_stage_nt<T, 1024, NS, 1, 2>(a, g, tiles, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        return hipErrorInvalidConfiguration;
+    }
+    if (g.rb != 1) return hipErrorInvalidValue;
     switch (cfg.nt) {
-        case 256: return launch_noise_stage_nt<T, 256, NS, 1>(a, g, tiles, s);
-        case 512: return launch_noise_stage_nt<T, 512, NS, 1>(a, g, tiles, s);
+        case 256: return launch_noise_stage_nt<T, 256, NS, 1, 1>(a, g, tiles, s);
+        case 512: return launch_noise_stage_nt<T, 512, NS, 1, 1>(a, g, tiles, s);
         case 1024:  // double-precision tiles of 1024 vectors run 512 threads x 4 instead
-            if constexpr (sizeof(T) == 4) return launch_noise_stage_nt<T, 1024, NS, 1>(a, g, tiles, s);
+            if constexpr (sizeof(T) == 4) return launch_noise_stage_nt<T, 1024, NS, 1, 1>(a, g, tiles, s);
             return hipErrorInvalidConfiguration;
         default: return hipErrorInvalidValue;
     }
@@ -831,7 +883,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         for (int k = 0; k < a.plan->nstages; ++k) {
             const StagePlan::Stage& t = a.plan->st[k];
             StageGeom g{};
-            if (!stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, acc, &g)) return hipErrorInvalidValue;
+            if (!stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, acc, &g)) return hipErrorInvalidValue;
             plan[nstages++] = Stage{t.j0, t.ns, g, true};
         }
     } else {
@@ -1002,23 +1054,24 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
         for (int ns = 1; ns <= 3 && j + ns <= J && e == hipSuccess; ++ns) {
             if (best[j + ns] < 0.f) continue;
             // the two best tiles (least halo overhead) of each thread configuration
-            StageGeom all[48], cand[16];
-            const int na = stage_candidates<T>(n, j, ns, acc, all, 48);
+            // (threads, owned vectors, realisations per pass)
+            StageGeom all[kMaxCand], cand[24];
+            const int na = stage_candidates<T>(n, j, ns, acc, all, kMaxCand);
+            auto config = [&](const StageGeom& sg) {
+                const NoiseCfg cfg = noise_cfg(sg.tw * sg.th / Vec<T>::G);
+                return acc ? (cfg.nt * 8 + cfg.kv) * 4 + sg.rb : sg.nt;
+            };
             int nc = 0;
-            for (int i = 0; i < na && nc < 16; ++i) {
-                const int vec = all[i].tw * all[i].th / Vec<T>::G;
-                const int key = acc ? noise_cfg(vec).nt * 8 + noise_cfg(vec).kv : all[i].nt;
+            for (int i = 0; i < na && nc < 24; ++i) {
+                const int key = config(all[i]);
                 int same = 0;
-                for (int q = 0; q < nc; ++q) {
-                    const int vq = cand[q].tw * cand[q].th / Vec<T>::G;
-                    same += (acc ? noise_cfg(vq).nt * 8 + noise_cfg(vq).kv : cand[q].nt) == key;
-                }
+                for (int q = 0; q < nc; ++q) same += config(cand[q]) == key;
                 if (same < 2) cand[nc++] = all[i];
             }
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 StagePlan sub;
                 sub.nstages = 1;
-                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th};
+                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th, cand[c].rb};
                 StarletArgs<T> b = a;
                 b.plan = &sub;
                 if (j > 1 && b.planes_off) {  // grouped: later stages read the c buffers
@@ -1034,9 +1087,9 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e != hipSuccess) break;
                 if (tune_log())
-                    std::fprintf(stderr, "amap tune: n=%d J=%d %s batch=%d stage j0=%d ns=%d tile %dx%d: %.1f us\n",
+                    std::fprintf(stderr, "amap tune: n=%d J=%d %s batch=%d stage j0=%d ns=%d tile %dx%d rb=%d: %.1f us\n",
                                  n, J, acc ? "noise" : "signal", a.batch, j, ns, cand[c].tw,
-                                 cand[c].th, 1e3f * ms / reps);
+                                 cand[c].th, cand[c].rb, 1e3f * ms / reps);
                 const float t = ms / reps + best[j + ns];
                 if (best[j] < 0.f || t < best[j]) {
                     best[j] = t;
