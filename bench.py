@@ -350,7 +350,7 @@ def main():
         step()
     torch.cuda.synchronize()
     ktimes = ctx.timing_read(reset=True)
-    B = min(R_REAL, max(1, (1 << 25) // (N * N)))
+    B = amap.noise_batch(N, R_REAL)
     kernels = {}
     for name, (launches, tot_ms) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
         kernels[name] = {"launches_per_step": launches / args.steps,

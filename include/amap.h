@@ -289,6 +289,12 @@ amap_status amap_plan_destroy(amap_plan_t plan);
  * admission policy budgets against). */
 size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real);
 
+/* Realisations the noise statistics of an n x n map process per launch
+ * sequence (the batch its kernels and workspace are sized for): about
+ * 2^27 pixels of realisations, at least 1 and at most n_real.  0 if n is not
+ * a supported side or n_real < 2. */
+int amap_noise_batch(int n, int n_real);
+
 /* ---- serving: continuous batching of independent jobs ---- */
 
 /* A request loop on one context.  The server allocates one arena of

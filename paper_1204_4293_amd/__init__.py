@@ -87,6 +87,7 @@ def load():
         "amap_batch_run": (I, [P, P]),
         "amap_plan_destroy": (I, [P]),
         "amap_job_footprint_bytes": (ctypes.c_size_t, [I, I, I, I]),
+        "amap_noise_batch": (I, [I, I]),
         "amap_server_create": (I, [P, I, ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
         "amap_server_submit": (I, [P, ctypes.POINTER(AmapJob), ctypes.POINTER(ctypes.c_longlong)]),
         "amap_server_poll": (I, [P, ctypes.c_longlong, ctypes.POINTER(I)]),
@@ -140,6 +141,11 @@ def _side(t):
 
 def job_footprint_bytes(dtype, n, J, n_real):
     return int(load().amap_job_footprint_bytes(dtype, n, J, n_real))
+
+
+def noise_batch(n, n_real):
+    """Realisations per launch sequence of the noise statistics (0: invalid)."""
+    return int(load().amap_noise_batch(int(n), int(n_real)))
 
 
 class Context:

@@ -331,7 +331,10 @@ amap_status enqueue_starlet(const amap_ctx* ctx, int logn, int J, int batch, con
 // Realisations per launch sequence of the noise loop.
 int noise_batch(int n, int n_real) {
     const long long n2 = (long long)n * n;
-    long long b = (1ll << 25) / n2;  // ~32 M pixels of realisations in flight
+    // ~128 M pixels of realisations in flight: fewer merges of the float64
+    // running statistics (each reads and writes them once) and fewer launch
+    // tails; 4.5 GiB of workspace at 1024^2
+    long long b = (1ll << 27) / n2;
     if (b < 1) b = 1;
     if (b > n_real) b = n_real;
     return (int)b;
@@ -899,6 +902,11 @@ size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real) {
     std::memset(&j, 0, sizeof j);
     j.n = n; j.J = J; j.n_real = n_real >= 2 ? n_real : 0;
     return job_workspace_bytes(dt, j);
+}
+
+int amap_noise_batch(int n, int n_real) {
+    if (check_n(n) != AMAP_OK || n_real < 2) return 0;
+    return noise_batch(n, n_real);
 }
 
 }  // extern "C"

@@ -431,12 +431,34 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
         }
     };
 
+    // the coarse values a round hands on are stored during the next round,
+    // before its loads are issued: waiting for a round's loads then never
+    // waits for stores issued after them.  Three-scale and four-vector
+    // stages have no registers to spare and store at once.
+    constexpr bool DEFER = NS < 3 && KV == 1;
+    VA keep[RB][KV];
+    auto store_coarse = [&](int i0p) {  // round starting at realisation i0p
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            if (i0p + t >= count) continue;
+            const int b = grp + (i0p + t) * a.groups;
+#pragma unroll
+            for (int k = 0; k < KV; ++k)
+                if (owner[k])
+                    vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), keep[t][k]);
+        }
+    };
+
 #pragma unroll
     for (int t = 0; t < RB; ++t)
         if (t < count) fetch(t, t);
     for (int ro = 0; ro < rounds; ++ro) {
         const int i0 = ro * RB;  // first realisation index of the round
         lds_barrier();  // the previous round is done with the tiles
+        // all of this round's loads are needed below; waiting for every
+        // outstanding memory operation here leaves none pending, so the
+        // loads issued next are not serialised behind conservative waits
+        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
             if (i0 + t >= count) continue;
@@ -449,6 +471,7 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                 }
             }
         }
+        if (DEFER && a.cout && ro > 0) store_coarse(i0 - RB);
 #pragma unroll
         for (int t = 0; t < RB; ++t)  // prefetch the next round's tiles
             if (i0 + RB + t < count) fetch(i0 + RB + t, t);
@@ -485,33 +508,56 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
         }
         if (a.cout) {
 #pragma unroll
-            for (int t = 0; t < RB; ++t) {
-                if (i0 + t >= count) continue;
-                const int b = grp + (i0 + t) * a.groups;
+            for (int t = 0; t < RB; ++t)
 #pragma unroll
-                for (int k = 0; k < KV; ++k)
-                    if (owner[k])
-                        vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), prev[t][k]);
-            }
+                for (int k = 0; k < KV; ++k) keep[t][k] = prev[t][k];
+            if (!DEFER) store_coarse(i0);
         }
     }
-    // merge into the running totals, or leave partials per group
+    if (DEFER && a.cout && rounds > 0) store_coarse((rounds - 1) * RB);
+    // merge into the running totals (all loads first: M and M2 do not
+    // overlap), or leave partials per group
+    if (a.groups == 1) {
+        const double na = (double)a.done, nb = (double)count, nt = na + nb;
+        const double fb = nb / nt, fab = na * nb / nt;
+        double* __restrict__ Mp = a.M;
+        double* __restrict__ Qp = a.M2;
 #pragma unroll
-    for (int k = 0; k < KV; ++k) {
-        if (!owner[k]) continue;
-        const long long base = owned_global(g, own_e[k]);
+        for (int k = 0; k < KV; ++k) {
+            if (!owner[k]) continue;
+            const long long base = owned_global(g, own_e[k]);  // a multiple of G
+            double2 mo[NS][G / 2], qo[NS][G / 2];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+            for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int c = 0; c < G; ++c) {
-                const long long gi = (long long)s * n2 + base + c;
-                if (a.groups == 1) {
-                    const double na = (double)a.done, nb = (double)count, nt = na + nb;
-                    const double delta = (double)mean[s][k][c] - a.M[gi];
-                    a.M[gi] += delta * (nb / nt);
-                    a.M2[gi] += (double)m2[s][k][c] + delta * delta * (na * nb / nt);
-                } else {
-                    AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
+                for (int h = 0; h < G / 2; ++h) {
+                    mo[s][h] = *reinterpret_cast<const double2*>(Mp + s * n2 + base + 2 * h);
+                    qo[s][h] = *reinterpret_cast<const double2*>(Qp + s * n2 + base + 2 * h);
+                }
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int h = 0; h < G / 2; ++h) {
+                    const double d0 = (double)mean[s][k][2 * h] - mo[s][h].x;
+                    const double d1 = (double)mean[s][k][2 * h + 1] - mo[s][h].y;
+                    mo[s][h].x += d0 * fb;
+                    mo[s][h].y += d1 * fb;
+                    qo[s][h].x += (double)m2[s][k][2 * h] + d0 * d0 * fab;
+                    qo[s][h].y += (double)m2[s][k][2 * h + 1] + d1 * d1 * fab;
+                    *reinterpret_cast<double2*>(Mp + s * n2 + base + 2 * h) = mo[s][h];
+                    *reinterpret_cast<double2*>(Qp + s * n2 + base + 2 * h) = qo[s][h];
+                }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            if (!owner[k]) continue;
+            const long long base = owned_global(g, own_e[k]);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
+#pragma unroll
+                for (int c = 0; c < G; ++c) {
                     pp[base + c] = mean[s][k][c];
                     pp[n2 + base + c] = m2[s][k][c];
                 }

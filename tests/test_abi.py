@@ -62,3 +62,13 @@ def test_create_without_device_reports_error():
     h = ctypes.c_void_p()
     st = lib.amap_create(0, ctypes.byref(h))
     assert st != 0 and not h.value
+
+
+def test_noise_batch_bounds():
+    assert amap.noise_batch(1024, 256) == 128
+    assert amap.noise_batch(1024, 40) == 40
+    assert amap.noise_batch(4096, 32) == 8
+    assert amap.noise_batch(64, 2) == 2
+    assert amap.noise_batch(8192, 32) == 0
+    assert amap.noise_batch(48, 32) == 0
+    assert amap.noise_batch(64, 1) == 0
