@@ -19,11 +19,11 @@
 // per-scale row and column kernels.
 //
 // Maps (or noise realisations) are spread over gridDim.y.  For noise maps the
-// stage writes its detail planes to a scratch stack and a streaming kernel
-// merges them into a running mean and sum of squared deviations per pixel
+// stages keep a running mean and sum of squared deviations per pixel
 // (Welford's update over the batch, then Chan, Golub & LeVeque's pairwise
 // merge in double precision), so no sum of squares of raw values is ever
-// formed.
+// formed: with few realisations a pixel's spread can be far below its mean,
+// and S2 - S1^2 / n would then lose most of its digits.
 #include <type_traits>
 
 #include "amap_device.h"
@@ -181,32 +181,22 @@ __device__ __forceinline__ int fdiv(int e, float inv_d) {
     return (int)(((float)e + 0.5f) * inv_d);
 }
 
-// Row and column passes of scale s of a stage on the tile in A (B is
-// scratch); on return A holds c_{j0+s} on the shrunken valid region
-// [xlo, xhi) x [vlo, vhi), which the call updates.  Work items are (row,
-// vector) pairs spread over all threads; each thread takes two row items at
-// a time so their LDS reads overlap.
-template <typename T, int NT, int RB = 1>
-__device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, int s, int& xlo,
-                                                int& xhi, int& vlo, int& vhi, int tstride = 0) {
+// Row pass A -> B of one dilation class over rows [vlo, vhi) of each of
+// the RB tiles: DXC = 1 or 2 (the five taps of a vector's G outputs lie in
+// it and its two neighbours) or 0 (the dilation is a multiple of the vector
+// width: five whole-vector taps).  Items are (row, vector) pairs spread over
+// all threads; each thread takes U at a time so their LDS reads overlap.
+template <typename T, int NT, int RB, int DXC, int U>
+__device__ __forceinline__ void row_pass(const T* A, T* Bf, int RS, int dx, int rlo4, int nv,
+                                         float inv_nv, int rtot, int vlo, int tstride) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
-    const int tid = threadIdx.x;
-    const int RS = g.RS;
-    const int dx = g.d0 << s, dv = 1 << s;
-    // row pass A -> B over rows [vlo, vhi), outputs [rlo, rhi) widened to
-    // whole vectors (the extra outputs stay outside the valid region)
-    const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
-    const int rlo4 = rlo / G * G;
-    const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
-    const float inv_nv = 1.0f / (float)nv;
-    const int rtot = nv * (vhi - vlo);
     // RB tiles share each pass: item e of tile t is e + t * rtot
-    for (int e0 = tid; e0 < RB * rtot; e0 += 2 * NT) {
-        VA o[2];
-        int off[2];
+    for (int e0 = threadIdx.x; e0 < RB * rtot; e0 += U * NT) {
+        VA o[U];
+        int off[U];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < U; ++u) {
             int e = e0 + u * NT;
             off[u] = -1;
             if (e < RB * rtot) {
@@ -216,7 +206,7 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
                 const int i0 = rlo4 + (e - r * nv) * G;
                 const T* ra = A + tb + (vlo + r) * RS;
                 off[u] = tb + (vlo + r) * RS + i0;
-                if (2 * dx <= G) {  // the five taps of all G outputs lie in three vectors
+                if constexpr (DXC != 0) {
                     const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
                              rr = vload<T, G>(ra + i0 + G);
                     T w[3 * G];
@@ -224,12 +214,10 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
                     for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
-                        const int b = G + k;
-                        o[u].e[k] = dx == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
-                                            : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
-                                                         w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
+                        const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
+                        o[u].e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
                     }
-                } else {  // dilation is a multiple of the vector width
+                } else {
                     o[u] = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
                                           vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
                                           vload<T, G>(ra + i0 + 2 * dx));
@@ -237,8 +225,38 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
             }
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < U; ++u)
             if (off[u] >= 0) vstore<T, G>(Bf + off[u], o[u]);
+    }
+}
+
+// Row and column passes of scale s of a stage on the tile in A (B is
+// scratch); on return A holds c_{j0+s} on the shrunken valid region
+// [xlo, xhi) x [vlo, vhi), which the call updates.  With RB > 1 the passes
+// cover RB tiles laid out tstride elements apart.  U: row items per thread
+// and iteration.
+template <typename T, int NT, int RB = 1, int U = 2>
+__device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, int s, int& xlo,
+                                                int& xhi, int& vlo, int& vhi, int tstride = 0) {
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    const int tid = threadIdx.x;
+    const int RS = g.RS;
+    const int dx = g.d0 << s, dv = 1 << s;
+    // row pass A -> B over rows [vlo, vhi), outputs [rlo, rhi) widened to
+    // whole vectors (the extra outputs stay outside the valid region); the
+    // dilation class is uniform, so the branch sits outside the item loop
+    const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
+    const int rlo4 = rlo / G * G;
+    const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row
+    const float inv_nv = 1.0f / (float)nv;
+    const int rtot = nv * (vhi - vlo);
+    if (dx == 1) {
+        row_pass<T, NT, RB, 1, U>(A, Bf, RS, dx, rlo4, nv, inv_nv, rtot, vlo, tstride);
+    } else if (2 * dx <= G) {
+        if constexpr (G >= 4) row_pass<T, NT, RB, 2, U>(A, Bf, RS, dx, rlo4, nv, inv_nv, rtot, vlo, tstride);
+    } else {
+        row_pass<T, NT, RB, 0, U>(A, Bf, RS, dx, rlo4, nv, inv_nv, rtot, vlo, tstride);
     }
     lds_barrier();
     // column pass B -> A: windows of kSegLen outputs along each chain
@@ -366,7 +384,7 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
 // Welford's running mean and sum of squared deviations of every owned pixel
 // and scale stay in registers; at the end they are merged (Chan's pairwise
 // update, double precision) into M, M2, or, with several groups, written as
-// float partials that k_merge_partials folds in group order.
+// partials that k_merge_partials folds in group order.
 template <typename T>
 struct NoiseStageArgs {
     int logn, j0, ns, log_tw, th;
@@ -485,7 +503,9 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
         int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
-            tile_scale_pass<T, NT, RB>(A, Bf, g, s, xlo, xhi, vlo, vhi, tstride);
+            // three scales of sums leave no registers for a second row item
+            tile_scale_pass<T, NT, RB, NS == 3 && sizeof(T) == 4 ? 1 : 2>(A, Bf, g, s, xlo, xhi, vlo, vhi,
+                                                                          tstride);
             // realisations in order, so the update sequence matches one at a time
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
