@@ -54,6 +54,10 @@ struct KsArgs {
     const long long* g1_off = nullptr;
     const long long* g2_off = nullptr;
     const long long* kE_off = nullptr;
+    // kappa_B not wanted (kB ignored): where supported, maps 2p and 2p+1
+    // share one inverse transform (their Hermitian parts packed as
+    // H_2p + i H_2p+1); C is overwritten either way.  Needs kE_off == null.
+    bool pair_e = false;
 };
 template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 

@@ -302,11 +302,12 @@ namespace amap {
 template <typename T>
 amap_status enqueue_ks(const amap_ctx* ctx, int logn, int batch, const T* g1, const T* g2,
                        long long g_stride, cpx<T>* C, T* kE, T* kB, long long out_stride,
-                       bool rotate, uint64_t seed, uint64_t r0, hipStream_t s) {
+                       bool rotate, uint64_t seed, uint64_t r0, hipStream_t s,
+                       bool pair_e = false) {
     KsArgs<T> a;
     a.logn = logn; a.batch = batch; a.g1 = g1; a.g2 = g2; a.g_stride = g_stride; a.C = C;
     a.kE = kE; a.kB = kB; a.out_stride = out_stride; a.rotate = rotate; a.seed = seed;
-    a.r0 = r0; a.tw = twiddles<T>(ctx); a.stream = s;
+    a.r0 = r0; a.tw = twiddles<T>(ctx); a.stream = s; a.pair_e = pair_e;
     AMAP_HIP(launch_ks<T>(a), "KS kernels");
     return AMAP_OK;
 }
@@ -380,7 +381,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
     for (int r0 = 0; r0 < n_real; r0 += B) {
         const int bb = (n_real - r0) < B ? (n_real - r0) : B;
         AMAP_TRY(enqueue_ks<T>(ctx, logn, bb, g1, g2, 0, C, kap, nullptr, n2, true, seed,
-                               (uint64_t)r0, s));
+                               (uint64_t)r0, s, /*pair_e=*/true));
         StarletArgs<T> a;
         a.logn = logn; a.J = J; a.batch = bb; a.done = r0; a.kappa = kap; a.in_stride = n2;
         a.planes = nullptr; a.planes_stride = 0; a.cbuf0 = cb0; a.cbuf1 = cb1; a.tmp = tmp;

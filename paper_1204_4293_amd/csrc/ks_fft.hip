@@ -394,20 +394,16 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
 }
 
 // ---- P2: rows: forward FFT along x, multiply by conj(D)/n^2, inverse (four-step) -
+// The work of one spectral row y for the N2 lanes t of a line, with E its
+// exchange region: on return a[n] holds the row's inverse transform at
+// x = t + N2 n.
 template <typename T, int LOGN>
-__global__ void __launch_bounds__((Row4<T, LOGN>::NT))
-k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
+__device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int y, int t,
+                                            cpx<T>* E, const cpx<T>* __restrict__ tw,
+                                            cpx<T> (&a)[FS<LOGN>::N1]) {
     using F = FS<LOGN>;
-    using R4 = Row4<T, LOGN>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR;
-    __shared__ cpx<T> ex[R4::LINES * R4::EX];
-    const int line = threadIdx.x / N2, t = threadIdx.x % N2;
-    if (line >= R4::LINES) return;  // no workgroup barrier follows
-    const int y = blockIdx.x * R4::LINES + line;
-    cpx<T>* row = C + (long long)blockIdx.y * N * N + (long long)y * N;
-    cpx<T>* E = ex + line * R4::EX;
     // forward, step 1: DFT_N1 over n1 of x[N2 n1 + t]
-    cpx<T> a[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = row[N2 * n1 + t];
     dft_reg<T, N1, false>(a);
@@ -458,15 +454,90 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) a[k1] = E[t * (N1 + 1) + k1];
     dft_reg<T, N1, true>(a);
+}
+
+template <typename T, int LOGN>
+__global__ void __launch_bounds__((Row4<T, LOGN>::NT))
+k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
+    using F = FS<LOGN>;
+    using R4 = Row4<T, LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2;
+    __shared__ cpx<T> ex[R4::LINES * R4::EX];
+    const int line = threadIdx.x / N2, t = threadIdx.x % N2;
+    if (line >= R4::LINES) return;  // no workgroup barrier follows
+    const int y = blockIdx.x * R4::LINES + line;
+    cpx<T>* row = C + (long long)blockIdx.y * N * N + (long long)y * N;
+    cpx<T> a[N1];
+    ks_row_line<T, LOGN>(row, y, t, ex + line * R4::EX, tw, a);
 #pragma unroll
     for (int n = 0; n < N1; ++n) row[t + N2 * n] = a[n];
+}
+
+// P2 for pairs of maps whose kappa_B is not wanted.  kappa_E of a map is
+// the inverse transform of the Hermitian part H(k) = [K(k) + conj(K(-k))]/2
+// of its spectrum K, which is real; two maps a, b then share one inverse
+// transform, of Z = H_a + i H_b, whose real and imaginary parts are their
+// kappa_E.  After the inverse transform along x, row y of the Hermitian
+// part is [c(y, x) + conj(c(-y, x))] / 2 with c the row's transform, so a
+// workgroup unit takes rows y and -y (rows 0 and n/2 are their own
+// partners) of both maps: four lines, one per (map, row), exchange their
+// rows through LDS and write the two rows of Z over map a's rows.  Pair p
+// holds maps 2p and 2p+1 (map 2p alone, read twice, if 2p+1 = batch).
+template <typename T, int LOGN>
+struct RowPair {
+    static constexpr int N2 = FS<LOGN>::N2, N = 1 << LOGN;
+    static constexpr int U0 = 128 / (4 * N2) > 0 ? 128 / (4 * N2) : 1;
+    static constexpr int UNITS = U0 > N / 2 ? N / 2 : U0;  // row pairs per workgroup
+    static constexpr int NT = UNITS * 4 * N2;
+};
+
+template <typename T, int LOGN>
+__global__ void __launch_bounds__((RowPair<T, LOGN>::NT))
+k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw) {
+    using F = FS<LOGN>;
+    using RP = RowPair<T, LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, EX = Row4<T, LOGN>::EX;
+    __shared__ cpx<T> ex[RP::UNITS * 4 * EX];
+    const int line = threadIdx.x / N2, t = threadIdx.x % N2;
+    const int u = line >> 2, role = line & 3;  // role: map (role >> 1), row (role & 1)
+    const int q = blockIdx.x * RP::UNITS + u;
+    const int r0 = q, r1 = q == 0 ? N / 2 : N - q;
+    const int ma = 2 * blockIdx.y;
+    const int mb = ma + 1 < batch ? ma + 1 : ma;
+    const int y = (role & 1) ? r1 : r0;
+    const cpx<T>* row = C + (long long)((role >> 1) ? mb : ma) * N * N + (long long)y * N;
+    cpx<T>* E = ex + line * EX;
+    cpx<T> a[N1];
+    ks_row_line<T, LOGN>(row, y, t, E, tw, a);
+    wave_lds_sync();
+#pragma unroll
+    for (int n = 0; n < N1; ++n) E[t + N2 * n] = a[n];
+    __syncthreads();  // all four rows of every unit are in LDS (and read from C)
+    // row (role & 1) of Z, half (role >> 1) of its x positions
+    const cpx<T>* base = ex + (u * 4) * EX;
+    const int self = role & 1, partner = q == 0 ? self : 1 - self;
+    const cpx<T>* caR = base + self * EX;
+    const cpx<T>* caP = base + partner * EX;
+    const cpx<T>* cbR = base + (2 + self) * EX;
+    const cpx<T>* cbP = base + (2 + partner) * EX;
+    cpx<T>* out = C + (long long)ma * N * N + (long long)y * N;
+    const T half = (T)0.5;
+#pragma unroll
+    for (int j = 0; j < N1 / 2; ++j) {
+        const int x = t + N2 * (j + (role >> 1) * (N1 / 2));
+        const cpx<T> p = caR[x], pc = caP[x], v = cbR[x], vc = cbP[x];
+        const T har = (p.x + pc.x) * half, hai = (p.y - pc.y) * half;
+        const T hbr = (v.x + vc.x) * half, hbi = (v.y - vc.y) * half;
+        out[x] = make_cpx(har - hbi, hai + hbr);
+    }
 }
 
 // ---- P3: inverse FFT along y (four-step), split real/imaginary -----------------
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
-k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ kB,
-              long long out_stride, const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw) {
+k_ks_cols_inv(const cpx<T>* __restrict__ C, long long in_stride, T* __restrict__ kE,
+              T* __restrict__ kB, long long out_stride, int kB_count,
+              const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw) {
     using F = FS<LOGN>;
     using S = Strip4<T, LOGN>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W;
@@ -474,7 +545,7 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
     const int b = blockIdx.y;
     const int x0 = blockIdx.x * W;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
-    const cpx<T>* in = C + (long long)b * N * N + x0 + c;
+    const cpx<T>* in = C + (long long)b * in_stride + x0 + c;
     cpx<T> a[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = in[(long long)(N2 * n1 + t) * N];
@@ -485,7 +556,7 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
     });
     __syncthreads();
     T* oe = kE + (kE_off ? kE_off[b] : (long long)b * out_stride) + x0 + c;
-    T* ob = kB ? kB + (long long)b * out_stride + x0 + c : nullptr;
+    T* ob = (kB && b < kB_count) ? kB + (long long)b * out_stride + x0 + c : nullptr;
 #pragma unroll
     for (int r = 0; r < F::RR; ++r) {
         const int k1 = t + N2 * r;
@@ -508,6 +579,14 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, T* __restrict__ kE, T* __restrict__ 
 // four-step register kernels.
 template <typename T, int LOGN>
 constexpr bool use_generic() { return sizeof(T) == 8 && LOGN >= 10; }
+
+// Pairs of maps share the inverse transform where the four-step kernels run
+// and the four exchange rows of a unit fit the 64 KiB of static LDS.
+template <typename T, int LOGN>
+constexpr bool pair_ok() {
+    return !use_generic<T, LOGN>() &&
+           (size_t)RowPair<T, LOGN>::UNITS * 4 * Row4<T, LOGN>::EX * sizeof(cpx<T>) <= 65536;
+}
 
 template <typename T, int LOGN>
 static hipError_t ks_launch_n(const KsArgs<T>& a) {
@@ -541,10 +620,26 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
             AMAP_LAUNCH("ks_cols_fwd", a.stream,
                         k_ks_cols_fwd<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
                             a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
+        if constexpr (pair_ok<T, LOGN>()) {
+            if (a.pair_e) {
+                using RP = RowPair<T, LOGN>;
+                if (a.kE_off || a.batch < 1) return hipErrorInvalidValue;
+                const int pairs = (a.batch + 1) / 2;
+                AMAP_LAUNCH("ks_rows_pair", a.stream,
+                            k_ks_rows_pair<T, LOGN><<<dim3((N / 2) / RP::UNITS, pairs), RP::NT, 0, a.stream>>>(
+                                a.C, a.batch, a.tw));
+                AMAP_LAUNCH("ks_cols_inv", a.stream,
+                            k_ks_cols_inv<T, LOGN><<<dim3(N / S::W, pairs), S::NT, 0, a.stream>>>(
+                                a.C, 2ll * N * N, a.kE, a.kE + a.out_stride, 2 * a.out_stride,
+                                a.batch / 2, nullptr, a.tw));
+                return hipGetLastError();
+            }
+        }
         AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
         AMAP_LAUNCH("ks_cols_inv", a.stream,
-                    k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
-                                                                        a.out_stride, a.kE_off, a.tw));
+                    k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(
+                        a.C, (long long)N * N, a.kE, a.pair_e ? nullptr : a.kB, a.out_stride, a.batch,
+                        a.kE_off, a.tw));
     }
     return hipGetLastError();
 }
