@@ -52,17 +52,25 @@ def kernel_model(name, n, J, batch_real, stage_starts=()):
     19 per pixel and starlet scale (two 5-tap B3 filters and a difference),
     4 per pixel and scale for the running mean and squared deviation.
     ``stage_starts`` lists the first scale of each noise stage (from the
-    kernel names), which fixes how many scales a stage covers.
+    kernel names), which fixes how many scales a stage covers.  The
+    signal's kernels (ks_cols_fwd, ks_rows, ks_cols_inv, starlet_stage_*)
+    take one map; the noise kernels take the batch, two realisations per
+    inverse transform (ks_rows_pair, ks_cols_inv_pair).
     """
     n2 = float(n * n)
     lg = n.bit_length() - 1
     B = batch_real
+    P = (B + 1) // 2  # realisation pairs
     fft1d = 5.0 * n2 * lg  # n transforms of length n
     models = {
         "ks_cols_fwd_rotate": (8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 6.0 * n2)),
         "ks_cols_fwd": (16.0 * n2, fft1d),
-        "ks_rows": (16.0 * n2 * B, B * (2 * fft1d + 6.0 * n2)),
-        "ks_cols_inv": (12.0 * n2 * B, B * fft1d),
+        "ks_rows": (16.0 * n2, 2 * fft1d + 6.0 * n2),
+        "ks_cols_inv": (12.0 * n2, fft1d),
+        # read B spectra, write P packed ones; B forward, P inverse transforms
+        "ks_rows_pair": (8.0 * n2 * (B + P), B * (fft1d + 6.0 * n2) + P * fft1d),
+        # read P packed spectra, write B real maps
+        "ks_cols_inv_pair": (8.0 * n2 * P + 4.0 * n2 * B, P * fft1d),
         "noise_finalize": ((16.0 + 12.0) * (J - 1) * n2, 3.0 * (J - 1) * n2),
         "count_peaks": (4.0 * (J - 1) * n2, 9.0 * (J - 1) * n2),
     }

@@ -628,7 +628,7 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
                 AMAP_LAUNCH("ks_rows_pair", a.stream,
                             k_ks_rows_pair<T, LOGN><<<dim3((N / 2) / RP::UNITS, pairs), RP::NT, 0, a.stream>>>(
                                 a.C, a.batch, a.tw));
-                AMAP_LAUNCH("ks_cols_inv", a.stream,
+                AMAP_LAUNCH("ks_cols_inv_pair", a.stream,
                             k_ks_cols_inv<T, LOGN><<<dim3(N / S::W, pairs), S::NT, 0, a.stream>>>(
                                 a.C, 2ll * N * N, a.kE, a.kE + a.out_stride, 2 * a.out_stride,
                                 a.batch / 2, nullptr, a.tw));
