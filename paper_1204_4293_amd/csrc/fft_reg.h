@@ -56,21 +56,23 @@ constexpr int bitrev(int i, int bits) {
 
 // One radix-2 butterfly of a length-LEN stage with twiddle W_LEN^K
 // (exp(-2 pi i K/LEN) forward, conjugate inverse); trivial twiddles cost no
-// multiplication.
+// multiplication.  Others take six fused multiply-adds: x' = x + w y as two
+// chained FMAs per component, then y' = 2 x - x' (which differs from x - w y
+// only by the rounding of x').
 template <typename T, bool INV, int LEN, int K>
 __host__ __device__ __forceinline__ void bfly(cpx<T>& x, cpx<T>& y) {
-    cpx<T> t;
-    if constexpr (K == 0) {
-        t = y;
-    } else if constexpr (4 * K == LEN) {
-        t = rot90<T, INV>(y);
+    if constexpr (K == 0 || 4 * K == LEN) {
+        const cpx<T> t = K == 0 ? y : rot90<T, INV>(y);
+        y = x - t;
+        x = x + t;
     } else {
         constexpr CS w = cos_sin_2pi(K, LEN);
         const T wr = (T)w.c, wi = INV ? (T)w.s : (T)-w.s;
-        t = make_cpx(wr * y.x - wi * y.y, wr * y.y + wi * y.x);
+        const T xr = (T)fma(wr, y.x, (T)fma(-wi, y.y, x.x));
+        const T xi = (T)fma(wr, y.y, (T)fma(wi, y.x, x.y));
+        y = make_cpx<T>((T)fma((T)2, x.x, -xr), (T)fma((T)2, x.y, -xi));
+        x = make_cpx<T>(xr, xi);
     }
-    y = x - t;
-    x = x + t;
 }
 
 template <typename T, bool INV, int LEN, int... I>
