@@ -496,6 +496,9 @@ def main():
         "direct_vs_starlet": direct,
         "roofline": roofline,
         "kernels": kernels,
+        # tile schedules the autotuner chose for this run: [j0, scales, tile
+        # width, tile sub-rows, realisations per LDS pass] per stage
+        "schedules": ctx.plans(),
     }
     ctx.close()
     if args.cpu_seconds > 0:
