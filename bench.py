@@ -490,8 +490,11 @@ def main():
                                "256 randomised noise realisations + sigma, S/N, peaks (S/N>3)",
                    "n": N, "J": J, "n_real": R_REAL, "batch_realisations": B},
         "wall_s_timed": wall,
-        "hbm_alg_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
-                        / (HBM_PEAK_GBS * 1e9),
+        # the job's compulsory HBM bytes (shear in; planes, sigma and S/N out:
+        # the realisations never leave the device) per step, as a fraction
+        # of HBM peak: the path is nowhere near bound by its inputs and outputs
+        "compulsory_hbm_frac": (N * N * (8 + 4 * J) + 8 * (J - 1) * N * N) / (ms_per_step * 1e-3)
+                               / (HBM_PEAK_GBS * 1e9),
         "plain": plain, "batched": batched, "served": served, "statistics": stats,
         "direct_vs_starlet": direct,
         "roofline": roofline,
