@@ -82,28 +82,15 @@ __device__ __forceinline__ void philox_block_u32(uint64_t seed, uint64_t r, uint
     }
 }
 
-// sin and cos of 2 pi w / 2^24 for a 24-bit integer w, single precision.
-// The top three bits of w select the octant exactly; the low 21 bits give a
-// fraction t of it, and the angle a = (pi/4) t (even octants) or
-// (pi/4)(1 - t) (odd octants, reflected exactly in integers) lies in
-// [0, pi/4].  sin a and cos a come from their Taylor series through a^9 and
-// a^10 (truncation below 2e-9 there), and the octant's symmetry maps them to
-// sin and cos of the full angle: within 1e-7 of the true values for every w.
+// sin and cos of 2 pi w / 2^24 for a 24-bit integer w, single precision:
+// w / 2^24 is exact in float and is the angle in turns, the unit of the
+// hardware sine and cosine instructions.  Over all 2^24 inputs their
+// results are within 1.3e-7 of the true values (checked exhaustively on
+// gfx950 against double precision).
 __device__ __forceinline__ void sincos_turn24(uint32_t w, float& sn, float& cs) {
-    const uint32_t o = w >> 21;
-    uint32_t f = w & 0x1FFFFFu;
-    if (o & 1u) f = 0x200000u - f;
-    const float a = (float)f * (0.78539816339744831f / 2097152.0f);
-    const float a2 = a * a;
-    const float s = a * fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.0f / 362880.0f, -1.0f / 5040.0f),
-                                                1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
-    const float c = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, -1.0f / 3628800.0f, 1.0f / 40320.0f),
-                                                    -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
-    // octants 1, 2, 5, 6 swap sin and cos; sin < 0 in octants 4-7, cos < 0 in 2-5
-    const bool swap = ((o + 1u) & 2u) != 0u;
-    const float x = swap ? c : s, y = swap ? s : c;
-    sn = (o & 4u) ? -x : x;
-    cs = ((o + 2u) & 4u) ? -y : y;
+    const float t = (float)w * (1.0f / 16777216.0f);
+    sn = __builtin_amdgcn_sinf(t);
+    cs = __builtin_amdgcn_cosf(t);
 }
 
 // Rotation of a shear value by beta = 2 pi u, u = (v >> 8) 2^-24.
