@@ -96,13 +96,19 @@ size_t amap_workspace_bytes(amap_ctx_t ctx);
  * schedule except, for noise statistics, in the rounding of how per-group
  * partial statistics are merged.  enable = 0 uses the analytic planner
  * (fewest stages, least halo overhead) and keeps existing tuned schedules
- * unused until it is enabled again. */
+ * unused until it is enabled again; enable = 2 uses the analytic planner
+ * for noise statistics too, but ends them with a final stage on whole
+ * sub-grids wherever one applies (a fixed schedule that always exercises
+ * that stage).  Other values: AMAP_E_INVAL. */
 amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
 
 /* Writes the context's tuned schedules as JSON into buf (len bytes including
- * the NUL): [{"elem": bytes per value, "logn", "J", "noise": 0|1, "batch",
+ * the NUL): [{"mode": 1 (tuned) | 2 (analytic with sub-grid final stage, see
+ * amap_set_autotune), "elem": bytes per value, "logn", "J", "noise": 0|1, "batch",
  * "stages": [[j0, ns, tile width, tile sub-rows, realisations per LDS
- * pass], ...]}, ...]; an empty
+ * pass, sub-grid stage 0|1], ...]}, ...]; a sub-grid stage is a final noise
+ * stage on whole periodic sub-grids of 2^(j0-1) (width and sub-rows are the
+ * sub-grid side); an empty
  * stage list means the analytic planner is used for that shape.
  * AMAP_E_INVAL if it does not fit. */
 amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);

@@ -180,7 +180,10 @@ class Context:
         return json.loads(buf.value.decode())
 
     def set_autotune(self, enable=True):
-        _check(load().amap_set_autotune(self._h, 1 if enable else 0))
+        """True/1: tuned schedules; False/0: analytic planner; 2: analytic
+        planner with sub-grid final noise stages where they apply."""
+        mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        _check(load().amap_set_autotune(self._h, mode))
 
     def timing_enable(self, enable=True):
         _check(load().amap_timing_enable(self._h, 1 if enable else 0))

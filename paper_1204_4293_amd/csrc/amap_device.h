@@ -37,6 +37,18 @@ __host__ __device__ __forceinline__ cpx<T> rot90(cpx<T> a) {
     return INV ? make_cpx(-a.y, a.x) : make_cpx(a.y, -a.x);
 }
 
+// Sub-grid order of an n x n plane for d = 2^logd: pixel (x, y) belongs to
+// sub-grid (p, q) = (x mod d, y mod d), an m x m periodic map (m = n / d) at
+// (x', y') = (x / d, y / d); the plane holds the d^2 sub-grids one after the
+// other, sub-grid (p, q) at (q d + p) m^2, row-major inside.  idx is the
+// row-major index y n + x.
+__host__ __device__ __forceinline__ long long subgrid_index(long long idx, int logn, int logd) {
+    const int logm = logn - logd;
+    const long long x = idx & ((1ll << logn) - 1), y = idx >> logn;
+    const long long dm = (1ll << logd) - 1;
+    return ((((y & dm) << logd) | (x & dm)) << (2 * logm)) | ((y >> logd) << logm) | (x >> logd);
+}
+
 // ---- Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11) ----------------
 struct u64x4 { uint64_t v[4]; };
 

@@ -70,10 +70,14 @@ template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 // 3*batch*n*n, the detail planes of one stage.
 // A starlet stage schedule: stage k covers scales st[k].j0 .. j0+ns-1 with
 // an LDS tile of tw pixels by th sub-rows, rb realisations per LDS pass
-// (noise stages; 1 otherwise).  nstages == 0: use the analytic planner.
+// (noise stages; 1 otherwise); sub = 1 marks a final noise stage on whole
+// sub-grids of d0 = 2^(j0-1) (tw = th = n / d0), whose input and running
+// statistics are in sub-grid order.  nstages == 0: use the analytic planner.
 struct StagePlan {
     int nstages = 0;
-    struct Stage { int j0, ns, tw, th, rb; } st[16];
+    struct Stage { int j0, ns, tw, th, rb, sub; } st[16];
+    // first scale whose running statistics are in sub-grid order (0: none)
+    int subgrid_j0() const { return nstages > 0 && st[nstages - 1].sub ? st[nstages - 1].j0 : 0; }
 };
 
 template <typename T>
@@ -104,6 +108,8 @@ template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
 // True when every stage of an n x n, J-plane transform has an LDS tile
 // (grouped maps need it).
 template <typename T> bool starlet_all_tiled(int n, int J);
+// The analytic noise schedule ending in a sub-grid final stage, if one applies.
+template <typename T> bool analytic_subgrid_plan(int n, int J, StagePlan* out);
 template <typename T>
 hipError_t launch_peak_hist(int logn, int nplanes, const T* planes, int sign, double lo,
                             double width, int nbins, long long* hist, hipStream_t s);
@@ -124,7 +130,8 @@ hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStrea
 // sigma = sqrt(M2/(R-1)); snr = w/sigma (0 where sigma = 0) if snr
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
-                                 const T* planes_signal, T* sigma, T* snr, hipStream_t s);
+                                 const T* planes_signal, T* sigma, T* snr, hipStream_t s,
+                                 int subgrid_j0 = 0);
 hipError_t launch_zero_f64(double* p, long long count, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long count, hipStream_t s);
 

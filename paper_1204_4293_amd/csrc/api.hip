@@ -167,7 +167,8 @@ struct amap_ctx {
     // tuned starlet schedules: (element size, log2 n, J, noise mode, batch) -> plan
     // (nstages == 0: the analytic planner)
     mutable std::map<std::array<int, 5>, StagePlan> plans;
-    bool autotune = true;
+    int autotune = 1;  // 0 analytic, 1 tuned, 2 analytic with sub-grid final noise stages
+    mutable std::map<std::array<int, 5>, StagePlan> plans_sub;  // mode 2 schedules
 };
 
 namespace {
@@ -177,8 +178,17 @@ namespace {
 // the stream is being captured; then the analytic plan is used.
 template <typename T>
 const StagePlan* tuned_plan(const amap_ctx* c, const StarletArgs<T>& a) {
-    if (!c->autotune) return nullptr;
+    if (c->autotune == 0) return nullptr;
     const std::array<int, 5> key{(int)sizeof(T), a.logn, a.J, a.M != nullptr, a.batch};
+    if (c->autotune == 2) {
+        if (!a.M) return nullptr;
+        auto is = c->plans_sub.find(key);
+        if (is != c->plans_sub.end()) return is->second.nstages ? &is->second : nullptr;
+        StagePlan p;
+        analytic_subgrid_plan<T>(1 << a.logn, a.J, &p);
+        StagePlan& kept = (c->plans_sub[key] = p);
+        return kept.nstages ? &kept : nullptr;
+    }
     auto it = c->plans.find(key);
     if (it != c->plans.end()) return &it->second;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -388,7 +398,8 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
         a.wbuf = wb; a.M = M; a.M2 = M2; a.part = part; a.stream = s; a.plan = plan;
         AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
-    AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s),
+    AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s,
+                                      plan ? plan->subgrid_j0() : 0),
              "noise finalize");
     return AMAP_OK;
 }
@@ -470,18 +481,20 @@ amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
     if (!buf || len == 0) return fail(AMAP_E_INVAL, "buf must not be NULL");
     std::string out = "[";
     bool first = true;
-    for (const auto& kv : c->plans) {
-        char item[160];
-        snprintf(item, sizeof item, "%s{\"elem\": %d, \"logn\": %d, \"J\": %d, \"noise\": %d, \"batch\": %d, \"stages\": [",
-                 first ? "" : ", ", kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4]);
-        out += item;
-        for (int k = 0; k < kv.second.nstages; ++k) {
-            const StagePlan::Stage& t = kv.second.st[k];
-            snprintf(item, sizeof item, "%s[%d, %d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th, t.rb);
+    for (int mode = 1; mode <= 2; ++mode) {
+        for (const auto& kv : mode == 1 ? c->plans : c->plans_sub) {
+            char item[192];
+            snprintf(item, sizeof item, "%s{\"mode\": %d, \"elem\": %d, \"logn\": %d, \"J\": %d, \"noise\": %d, \"batch\": %d, \"stages\": [",
+                     first ? "" : ", ", mode, kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4]);
             out += item;
+            for (int k = 0; k < kv.second.nstages; ++k) {
+                const StagePlan::Stage& t = kv.second.st[k];
+                snprintf(item, sizeof item, "%s[%d, %d, %d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th, t.rb, t.sub);
+                out += item;
+            }
+            out += "]}";
+            first = false;
         }
-        out += "]}";
-        first = false;
     }
     out += "]";
     if (out.size() + 1 > len) {
@@ -495,7 +508,8 @@ amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
 amap_status amap_set_autotune(amap_ctx_t c, int enable) {
     g_last_error.clear();
     if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
-    c->autotune = enable != 0;
+    if (enable < 0 || enable > 2) return fail(AMAP_E_INVAL, "autotune mode must be 0, 1 or 2");
+    c->autotune = enable;
     return AMAP_OK;
 }
 
@@ -1073,7 +1087,7 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
             st = fail(AMAP_E_HIP, "cannot upload map tables");
         }
     }
-    if (st == AMAP_OK && c->autotune) {
+    if (st == AMAP_OK && c->autotune == 1) {
         // one direct run on the null stream tunes (and caches) the starlet
         // schedule of every group and job shape before any graph capture
         st = enqueue_plan(p, nullptr);

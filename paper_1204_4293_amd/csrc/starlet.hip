@@ -395,6 +395,7 @@ struct NoiseStageArgs {
     double* M2;
     void* part;              // [groups][ns][2][n^2] partials (accumulator type) when groups > 1
     float inv_tvec;          // 1 / (vectors per tile row), for index splitting
+    int cout_logd = 0;       // > 0: cout in sub-grid order for d = 2^cout_logd (subgrid_index)
 };
 
 // Single-precision one-vector stages of 256 or 512 threads keep to 128
@@ -461,9 +462,17 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
             if (i0p + t >= count) continue;
             const int b = grp + (i0p + t) * a.groups;
 #pragma unroll
-            for (int k = 0; k < KV; ++k)
-                if (owner[k])
-                    vstore<T, G>(a.cout + (long long)b * n2 + owned_global(g, own_e[k]), keep[t][k]);
+            for (int k = 0; k < KV; ++k) {
+                if (!owner[k]) continue;
+                T* dst = a.cout + (long long)b * n2;
+                const long long gi = owned_global(g, own_e[k]);
+                if (a.cout_logd == 0) {
+                    vstore<T, G>(dst + gi, keep[t][k]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < G; ++c) dst[subgrid_index(gi + c, a.logn, a.cout_logd)] = keep[t][k].e[c];
+                }
+            }
         }
     };
 
@@ -581,6 +590,135 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                     pp[base + c] = mean[s][k][c];
                     pp[n2 + base + c] = m2[s][k][c];
                 }
+            }
+        }
+    }
+}
+
+// Noise mode, final stage on whole sub-grids.  From scale j0 on, with
+// d0 = 2^(j0-1), every tap of every remaining scale stays inside one
+// sub-grid of d0 (subgrid_index): scale j0 + s is the same B3 cascade on the
+// m x m periodic sub-grid at dilation 2^s.  A workgroup holds one sub-grid
+// in LDS, so there is no halo and the wrap is an index mask; each thread
+// owns one vector, computes it in both passes of every scale and keeps its
+// Welford state (same update as the tile stages) in registers.  src holds
+// c_{j0-1} of realisation b at src + b n^2 in sub-grid order, M and M2 the
+// stage's planes in sub-grid order.  Grid (d0^2 sub-grids, groups).
+template <typename T>
+struct NoiseSubArgs {
+    int logn, j0;
+    const T* src;
+    int batch, groups, done;
+    double* M;
+    double* M2;
+    void* part;  // [groups][ns][2][n^2] partials when groups > 1
+};
+
+template <typename T, int LOGM, int NS>
+__global__ void __launch_bounds__((1 << (2 * LOGM)) / Vec<T>::G)
+k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
+    constexpr int G = Vec<T>::G;
+    constexpr int M = 1 << LOGM, MV = M / G;   // side, vectors per row
+    constexpr int RS = M + G;                  // LDS row stride
+    using VA = VArr<T, G>;
+    using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+    __shared__ __align__(16) T A[M * RS];
+    __shared__ __align__(16) T B[M * RS];
+    const long long n2 = 1ll << (2 * a.logn);
+    const int grp = blockIdx.y;
+    const int count = (a.batch - grp + a.groups - 1) / a.groups;
+    const int yo = threadIdx.x / MV, xo = (threadIdx.x % MV) * G;  // the owned vector
+    const int own = yo * RS + xo;
+    const long long gown = ((long long)blockIdx.x << (2 * LOGM)) + (yo << LOGM) + xo;
+    AccT mean[NS][G], m2[NS][G];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < G; ++c) mean[s][c] = m2[s][c] = (AccT)0;
+    // three realisations in flight ahead of the one being transformed
+    auto fetch = [&](int i) {
+        const int ii = i < count ? i : count - 1;  // past the end: a harmless reload
+        return vload<T, G>(a.src + (long long)(grp + ii * a.groups) * n2 + gown);
+    };
+    VA pf0, pf1, pf2;
+    if (count > 0) { pf0 = fetch(0); pf1 = fetch(1); pf2 = fetch(2); }
+    for (int it = 0; it < count; ++it) {
+        VA prev = pf0;
+        pf0 = pf1; pf1 = pf2; pf2 = fetch(it + 3);
+        vstore<T, G>(A + own, prev);
+        __syncthreads();  // A complete; every read of B by the previous realisation done
+        const AccT inv = (AccT)1 / (AccT)(it + 1);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int d = 1 << s;  // dilation in sub-grid units
+            const T* ra = A + yo * RS;
+            VA o;
+            if (2 * d <= G) {  // the five taps of the G outputs lie in three vectors
+                const VA l = vload<T, G>(ra + ((xo - G) & (M - 1))), c = vload<T, G>(ra + xo),
+                         r = vload<T, G>(ra + ((xo + G) & (M - 1)));
+                T w[3 * G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = r.e[k]; }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int b = G + k;
+                    o.e[k] = d == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
+                                    : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
+                                                 w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
+                }
+            } else {  // the dilation is a multiple of the vector width
+                o = vcombine<T, G>(vload<T, G>(ra + ((xo - 2 * d) & (M - 1))), vload<T, G>(ra + ((xo - d) & (M - 1))),
+                                   vload<T, G>(ra + xo), vload<T, G>(ra + ((xo + d) & (M - 1))),
+                                   vload<T, G>(ra + ((xo + 2 * d) & (M - 1))));
+            }
+            vstore<T, G>(B + own, o);
+            __syncthreads();  // B complete
+            const VA c = vcombine<T, G>(vload<T, G>(B + ((yo - 2 * d) & (M - 1)) * RS + xo),
+                                        vload<T, G>(B + ((yo - d) & (M - 1)) * RS + xo),
+                                        vload<T, G>(B + yo * RS + xo),
+                                        vload<T, G>(B + ((yo + d) & (M - 1)) * RS + xo),
+                                        vload<T, G>(B + ((yo + 2 * d) & (M - 1)) * RS + xo));
+#pragma unroll
+            for (int cc = 0; cc < G; ++cc) {
+                const AccT x = (AccT)(prev.e[cc] - c.e[cc]);
+                const AccT dd = x - mean[s][cc];
+                mean[s][cc] = fma(dd, inv, mean[s][cc]);
+                m2[s][cc] = fma(dd, x - mean[s][cc], m2[s][cc]);
+            }
+            prev = c;
+            if (s + 1 < NS) {
+                vstore<T, G>(A + own, c);  // every row-pass read of A was before the last barrier
+                __syncthreads();           // A complete; every read of B done
+            }
+        }
+    }
+    // merge into the running totals, or leave partials per group
+    if (a.groups == 1) {
+        const double na = (double)a.done, nb = (double)count, nt = na + nb;
+        const double fb = nb / nt, fab = na * nb / nt;
+        double* __restrict__ Mp = a.M;
+        double* __restrict__ Qp = a.M2;
+        double mo[NS][G], qo[NS][G];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < G; ++c) { mo[s][c] = Mp[s * n2 + gown + c]; qo[s][c] = Qp[s * n2 + gown + c]; }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const double dl = (double)mean[s][c] - mo[s][c];
+                Mp[s * n2 + gown + c] = mo[s][c] + dl * fb;
+                Qp[s * n2 + gown + c] = qo[s][c] + ((double)m2[s][c] + dl * dl * fab);
+            }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            AccT* pp = static_cast<AccT*>(a.part) + ((long long)grp * NS + s) * 2 * n2;
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                pp[gown + c] = mean[s][c];
+                pp[n2 + gown + c] = m2[s][c];
             }
         }
     }
@@ -885,6 +1023,57 @@ static hipError_t launch_noise_stage(const NoiseStageArgs<T>& a, const StageGeom
     }
 }
 
+// Final noise stages on whole sub-grids: side m = n / d0 from 16 to 64
+// (float; 32 for double, whose vectors hold two values), at most four scales
+// (three for double, so that the partials of several groups stay within
+// starlet_partials_bytes).
+template <typename T>
+static bool subgrid_ok(int n, int j0, int J) {
+    const int ns = J - j0;
+    if (j0 < 1 || ns < 1 || ns > (sizeof(T) == 4 ? 4 : 3)) return false;
+    const int d0 = 1 << (j0 - 1);
+    if (d0 > n / 16) return false;
+    const int m = n / d0;
+    return m >= 16 && m <= (sizeof(T) == 4 ? 64 : 32);
+}
+
+template <typename T, int LOGM, int NS>
+static hipError_t launch_subgrid_nsm(const NoiseSubArgs<T>& a, int tiles, hipStream_t s) {
+    constexpr int NT = (1 << (2 * LOGM)) / Vec<T>::G;
+    static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
+                                    "noise_stage_j4", "noise_stage_j5", "noise_stage_j6",
+                                    "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
+                                    "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
+    AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                k_starlet_noise_subgrid<T, LOGM, NS><<<dim3(tiles, a.groups), NT, 0, s>>>(a));
+    return hipGetLastError();
+}
+
+template <typename T, int LOGM>
+static hipError_t launch_subgrid_m(const NoiseSubArgs<T>& a, int ns, int tiles, hipStream_t s) {
+    switch (ns) {
+        case 1: return launch_subgrid_nsm<T, LOGM, 1>(a, tiles, s);
+        case 2: return launch_subgrid_nsm<T, LOGM, 2>(a, tiles, s);
+        case 3: return launch_subgrid_nsm<T, LOGM, 3>(a, tiles, s);
+        case 4:
+            if constexpr (sizeof(T) == 4) return launch_subgrid_nsm<T, LOGM, 4>(a, tiles, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t launch_subgrid(const NoiseSubArgs<T>& a, int ns, int logm, int tiles, hipStream_t s) {
+    switch (logm) {
+        case 4: return launch_subgrid_m<T, 4>(a, ns, tiles, s);
+        case 5: return launch_subgrid_m<T, 5>(a, ns, tiles, s);
+        case 6:
+            if constexpr (sizeof(T) == 4) return launch_subgrid_m<T, 6>(a, ns, tiles, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // Workgroups of a noise stage: one per tile, times enough realisation groups
 // to give every CU work (256 of them), at most one group per realisation.
 static int noise_groups(int tiles, int batch) {
@@ -932,6 +1121,31 @@ bool starlet_all_tiled(int n, int J) {
     }
     return true;
 }
+// The analytic planner's noise stages up to the first scale from which a
+// sub-grid final stage applies, then that stage.  False if there is no such
+// scale or a stage before it has no LDS tile.
+template <typename T>
+bool analytic_subgrid_plan(int n, int J, StagePlan* out) {
+    out->nstages = 0;
+    int js = 0;  // the first scale a sub-grid stage can start at
+    for (int j = 1; j < J && !js; ++j)
+        if (subgrid_ok<T>(n, j, J)) js = j;
+    if (!js) return false;
+    for (int j0 = 1; j0 < js;) {
+        StageGeom g{};
+        if (!pick_stage<T>(n, j0, js - j0, true, &g) || out->nstages >= 15) {
+            out->nstages = 0;
+            return false;
+        }
+        out->st[out->nstages++] = StagePlan::Stage{j0, g.ns, g.tw, g.th, g.rb, 0};
+        j0 += g.ns;
+    }
+    out->st[out->nstages++] = StagePlan::Stage{js, J - js, n >> (js - 1), n >> (js - 1), 1, 1};
+    return true;
+}
+template bool analytic_subgrid_plan<float>(int, int, StagePlan*);
+template bool analytic_subgrid_plan<double>(int, int, StagePlan*);
+
 template bool starlet_all_tiled<float>(int, int);
 template bool starlet_all_tiled<double>(int, int);
 
@@ -941,7 +1155,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     const long long n2 = (long long)n * n;
     const bool acc = a.M != nullptr;
     // plan the stages: (j0, ns, tile) or a per-scale stage (tile.nt == 0)
-    struct Stage { int j0, ns; StageGeom g; bool tiled; };
+    struct Stage { int j0, ns; StageGeom g; bool tiled, sub; };
     Stage plan[16];
     int nstages = 0;
     if (a.plan && a.plan->nstages > 0) {
@@ -949,15 +1163,21 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         for (int k = 0; k < a.plan->nstages; ++k) {
             const StagePlan::Stage& t = a.plan->st[k];
             StageGeom g{};
+            if (t.sub) {  // a final noise stage on whole sub-grids
+                if (!acc || k + 1 != a.plan->nstages || t.j0 + t.ns != a.J || !subgrid_ok<T>(n, t.j0, a.J))
+                    return hipErrorInvalidValue;
+                plan[nstages++] = Stage{t.j0, t.ns, g, false, true};
+                continue;
+            }
             if (!stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, acc, &g)) return hipErrorInvalidValue;
-            plan[nstages++] = Stage{t.j0, t.ns, g, true};
+            plan[nstages++] = Stage{t.j0, t.ns, g, true, false};
         }
     } else {
         for (int j0 = 1; j0 < a.J; ) {
             StageGeom g{};
             const bool tiled = pick_stage<T>(n, j0, a.J - j0, acc, &g);
             const int ns = tiled ? g.ns : 1;
-            plan[nstages++] = Stage{j0, ns, g, tiled};
+            plan[nstages++] = Stage{j0, ns, g, tiled, false};
             j0 += ns;
         }
     }
@@ -1009,6 +1229,34 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         hipError_t e;
         int lt = 0;
         while ((1 << lt) < st.g.tw) ++lt;
+        if (st.sub) {  // acc only, the last stage: c and the statistics in sub-grid order
+            const int d0 = 1 << (st.j0 - 1);
+            const int tiles = d0 * d0;
+            int logm = 0;
+            while ((1 << logm) < n / d0) ++logm;
+            NoiseSubArgs<T> s;
+            s.logn = a.logn; s.j0 = st.j0; s.src = cur; s.batch = a.batch;
+            s.groups = noise_groups(tiles, a.batch); s.done = a.done;
+            s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
+            s.part = a.part;
+            {
+                using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+                if (s.groups > 1 && (size_t)s.groups * st.ns * 2 * (size_t)n2 * sizeof(AccT) >
+                                        starlet_partials_bytes(a.logn, a.batch))
+                    return hipErrorInvalidConfiguration;
+            }
+            e = launch_subgrid<T>(s, st.ns, logm, tiles, a.stream);
+            if (e == hipSuccess && s.groups > 1) {
+                using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+                AMAP_LAUNCH("merge_partials", a.stream,
+                            k_merge_partials<AccT><<<(unsigned)((n2 + 255) / 256), 256, 0, a.stream>>>(
+                                static_cast<const AccT*>(a.part), s.groups, st.ns, a.batch, a.done,
+                                n2, s.M, s.M2));
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) return e;
+            continue;
+        }
         if (st.tiled && acc) {
             const int d0 = 1 << (st.j0 - 1);
             const int tiles = (n / st.g.tw) * ((n / d0) / st.g.th) * d0;
@@ -1019,6 +1267,8 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
             s.part = a.part;
             s.inv_tvec = 1.0f / (float)((st.g.tw + 2 * stage_hx(d0, st.ns, Vec<T>::G)) / Vec<T>::G);
+            // a following sub-grid stage reads c in its sub-grid order
+            s.cout_logd = (gi + 1 < nstages && plan[gi + 1].sub) ? plan[gi + 1].j0 - 1 : 0;
             {
                 using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
                 if (s.groups > 1 && (size_t)s.groups * st.ns * 2 * (size_t)n2 * sizeof(AccT) >
@@ -1137,7 +1387,7 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 StagePlan sub;
                 sub.nstages = 1;
-                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th, cand[c].rb};
+                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th, cand[c].rb, 0};
                 StarletArgs<T> b = a;
                 b.plan = &sub;
                 if (j > 1 && b.planes_off) {  // grouped: later stages read the c buffers
@@ -1157,6 +1407,32 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
                                  n, J, acc ? "noise" : "signal", a.batch, j, ns, cand[c].tw,
                                  cand[c].th, cand[c].rb, 1e3f * ms / reps);
                 const float t = ms / reps + best[j + ns];
+                if (best[j] < 0.f || t < best[j]) {
+                    best[j] = t;
+                    pick[j] = sub.st[0];
+                }
+            }
+        }
+        if (acc && e == hipSuccess && subgrid_ok<T>(n, j, J)) {
+            // all remaining scales on whole sub-grids (a final stage)
+            const int m = n >> (j - 1);
+            StagePlan sub;
+            sub.nstages = 1;
+            sub.st[0] = StagePlan::Stage{j, J - j, m, m, 1, 1};
+            StarletArgs<T> b = a;
+            b.plan = &sub;
+            e = launch_starlet<T>(b);  // warm
+            if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_starlet<T>(b);
+            if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) {
+                if (tune_log())
+                    std::fprintf(stderr, "amap tune: n=%d J=%d noise batch=%d stage j0=%d ns=%d sub-grids %dx%d: %.1f us\n",
+                                 n, J, a.batch, j, J - j, m, m, 1e3f * ms / reps);
+                const float t = ms / reps;
                 if (best[j] < 0.f || t < best[j]) {
                     best[j] = t;
                     pick[j] = sub.st[0];

@@ -6,15 +6,20 @@
 
 namespace amap {
 
+// Planes of scale subgrid_j0 and above (0: none) hold M2 in sub-grid order
+// for d = 2^(subgrid_j0 - 1) (subgrid_index).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_noise_finalize(const double* __restrict__ M2, int R, int J, long long n2,
+k_noise_finalize(const double* __restrict__ M2, int R, int J, int logn, int subgrid_j0,
                  const T* __restrict__ planes_signal, T* __restrict__ sigma, T* __restrict__ snr) {
+    const long long n2 = 1ll << (2 * logn);
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= n2) return;
+    const long long sidx = subgrid_j0 > 0 ? subgrid_index(idx, logn, subgrid_j0 - 1) : idx;
     for (int j = 0; j < J - 1; ++j) {
         const long long e = (long long)j * n2 + idx;
-        double var = M2[e] / (double)(R - 1);
+        const bool sub = subgrid_j0 > 0 && j + 1 >= subgrid_j0;
+        double var = M2[(long long)j * n2 + (sub ? sidx : idx)] / (double)(R - 1);
         var = var > 0.0 ? var : 0.0;
         const T sg = (T)sqrt(var);
         sigma[e] = sg;
@@ -188,11 +193,13 @@ static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 
 
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
-                                 const T* planes_signal, T* sigma, T* snr, hipStream_t s) {
+                                 const T* planes_signal, T* sigma, T* snr, hipStream_t s,
+                                 int subgrid_j0) {
     const long long n2 = 1ll << (2 * logn);
+    if (subgrid_j0 < 0 || subgrid_j0 >= J) return hipErrorInvalidValue;
     AMAP_LAUNCH("noise_finalize", s,
-                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(M2, R, J, n2, planes_signal,
-                                                                   sigma, snr));
+                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(M2, R, J, logn, subgrid_j0,
+                                                                   planes_signal, sigma, snr));
     return hipGetLastError();
 }
 
@@ -256,9 +263,9 @@ hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, 
 }
 
 template hipError_t launch_noise_finalize<float>(int, int, int, const double*, const float*, float*,
-                                                 float*, hipStream_t);
+                                                 float*, hipStream_t, int);
 template hipError_t launch_noise_finalize<double>(int, int, int, const double*, const double*,
-                                                  double*, double*, hipStream_t);
+                                                  double*, double*, hipStream_t, int);
 template hipError_t launch_count_peaks<float>(int, int, const float*, double, long long*, hipStream_t);
 template hipError_t launch_count_peaks<double>(int, int, const double*, double, long long*, hipStream_t);
 template hipError_t launch_peak_hist<float>(int, int, const float*, int, double, double, int, long long*,
