@@ -401,7 +401,9 @@ struct NoiseStageArgs {
 // Single-precision one-vector stages of 256 or 512 threads keep to 128
 // registers, so that two or more workgroups share a CU and overlap each
 // other's barrier phases.
-template <typename T, int NT, int NS, int KV, int RB>
+// SG: the coarse output goes out in sub-grid order (a.cout_logd > 0), a
+// separate instantiation so that other stages carry none of its registers.
+template <typename T, int NT, int NS, int KV, int RB, bool SG>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && KV == 1 && NT <= 512) ? 4 : 1)
 k_starlet_noise_stage(NoiseStageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
@@ -456,6 +458,23 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
     // stages have no registers to spare and store at once.
     constexpr bool DEFER = NS < 3 && KV == 1;
     VA keep[RB][KV];
+    // Sub-grid order of the coarse output (for d = 2^cout_logd): where the
+    // tile width is a multiple of G d, a tile row holds, per sub-grid
+    // column p, whole vectors of G consecutive sub-grid pixels; the owned
+    // vector (row pv, index ix) then stands for vector xg = ix % per of
+    // sub-grid column p = ix / per (per = tw / (G d)), gathered from LDS
+    // and stored whole.  Otherwise each value is stored on its own.
+    const int sgd = SG ? 1 << a.cout_logd : 0;
+    const bool sg_vec = SG && g.tw % (G * sgd) == 0;
+    // the tile row and tile-relative column of that vector's first pixel
+    // (every factor is a power of two: shifts and masks only)
+    constexpr int LOG_G = G == 4 ? 2 : 1;
+    const int lper = g.log_tw - LOG_G - a.cout_logd;  // log2 per
+    auto sg_pos = [&](int e, int& pv, int& xr) {
+        pv = e >> g.log_tw;
+        const int ix = (e & (g.tw - 1)) >> LOG_G;
+        xr = (ix >> lper) + ((ix & ((1 << lper) - 1)) << (a.cout_logd + LOG_G));
+    };
     auto store_coarse = [&](int i0p) {  // round starting at realisation i0p
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
@@ -466,8 +485,13 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                 if (!owner[k]) continue;
                 T* dst = a.cout + (long long)b * n2;
                 const long long gi = owned_global(g, own_e[k]);
-                if (a.cout_logd == 0) {
+                if constexpr (!SG) {
                     vstore<T, G>(dst + gi, keep[t][k]);
+                } else if (sg_vec) {
+                    int pv, xr;
+                    sg_pos(own_e[k], pv, xr);
+                    vstore<T, G>(dst + subgrid_index(out_row(g, pv) + g.x0 + xr, a.logn, a.cout_logd),
+                                 keep[t][k]);
                 } else {
 #pragma unroll
                     for (int c = 0; c < G; ++c) dst[subgrid_index(gi + c, a.logn, a.cout_logd)] = keep[t][k].e[c];
@@ -539,7 +563,17 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
 #pragma unroll
             for (int t = 0; t < RB; ++t)
 #pragma unroll
-                for (int k = 0; k < KV; ++k) keep[t][k] = prev[t][k];
+                for (int k = 0; k < KV; ++k) {
+                    if (SG && sg_vec && owner[k]) {  // the tile is complete in LDS since the last barrier
+                        int pv, xr;
+                        sg_pos(own_e[k], pv, xr);
+                        const T* src = A + t * tstride + (g.Hv + pv) * g.RS + g.Hx + xr;
+#pragma unroll
+                        for (int c = 0; c < G; ++c) keep[t][k].e[c] = src[sgd * c];
+                    } else {
+                        keep[t][k] = prev[t][k];
+                    }
+                }
             if (!DEFER) store_coarse(i0);
         }
     }
@@ -958,11 +992,15 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                         hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV, RB>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV, RB, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_starlet_noise_stage<T, NT, NS, KV, RB, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
+    if (a.cout_logd < 0 || a.cout_logd >= a.logn) return hipErrorInvalidValue;
     {  // the tile must fit the prefetch registers and the owned vectors of the threads
         constexpr int G = Vec<T>::G;
         const int d0 = 1 << (a.j0 - 1);
@@ -975,8 +1013,12 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
                                     "noise_stage_j4", "noise_stage_j5", "noise_stage_j6",
                                     "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
                                     "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
-    AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
-                k_starlet_noise_stage<T, NT, NS, KV, RB><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+    if (a.cout_logd > 0)
+        AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                    k_starlet_noise_stage<T, NT, NS, KV, RB, true><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
+    else
+        AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                    k_starlet_noise_stage<T, NT, NS, KV, RB, false><<<dim3(tiles, a.groups), NT, g.lds, s>>>(a));
     return hipGetLastError();
 }
 
