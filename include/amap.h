@@ -98,8 +98,8 @@ size_t amap_workspace_bytes(amap_ctx_t ctx);
  * (fewest stages, least halo overhead) and keeps existing tuned schedules
  * unused until it is enabled again; enable = 2 uses the analytic planner
  * for noise statistics too, but ends them with a final stage on whole
- * sub-grids wherever one applies (a fixed schedule that always exercises
- * that stage).  Other values: AMAP_E_INVAL. */
+ * sub-grids (two realisations per pass) wherever one applies: a fixed
+ * schedule that always exercises that stage.  Other values: AMAP_E_INVAL. */
 amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
 
 /* Writes the context's tuned schedules as JSON into buf (len bytes including

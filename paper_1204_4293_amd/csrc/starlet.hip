@@ -646,18 +646,21 @@ struct NoiseSubArgs {
     double* M;
     double* M2;
     void* part;  // [groups][ns][2][n^2] partials when groups > 1
+    int rb;      // realisations per pass (1 or 2)
 };
 
-template <typename T, int LOGM, int NS>
+template <typename T, int LOGM, int NS, int RB>
 __global__ void __launch_bounds__((1 << (2 * LOGM)) / Vec<T>::G)
 k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
     constexpr int G = Vec<T>::G;
     constexpr int M = 1 << LOGM, MV = M / G;   // side, vectors per row
     constexpr int RS = M + G;                  // LDS row stride
+    constexpr int TS = M * RS;                 // LDS tile stride (RB tiles per pass)
     using VA = VArr<T, G>;
     using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
-    __shared__ __align__(16) T A[M * RS];
-    __shared__ __align__(16) T B[M * RS];
+    extern __shared__ __align__(16) unsigned char sub_smem[];  // subgrid_lds_bytes
+    T* A = reinterpret_cast<T*>(sub_smem);
+    T* B = A + RB * TS;
     const long long n2 = 1ll << (2 * a.logn);
     const int grp = blockIdx.y;
     const int count = (a.batch - grp + a.groups - 1) / a.groups;
@@ -669,61 +672,80 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
     for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int c = 0; c < G; ++c) mean[s][c] = m2[s][c] = (AccT)0;
-    // three realisations in flight ahead of the one being transformed
     auto fetch = [&](int i) {
         const int ii = i < count ? i : count - 1;  // past the end: a harmless reload
         return vload<T, G>(a.src + (long long)(grp + ii * a.groups) * n2 + gown);
     };
-    VA pf0, pf1, pf2;
-    if (count > 0) { pf0 = fetch(0); pf1 = fetch(1); pf2 = fetch(2); }
-    for (int it = 0; it < count; ++it) {
-        VA prev = pf0;
-        pf0 = pf1; pf1 = pf2; pf2 = fetch(it + 3);
-        vstore<T, G>(A + own, prev);
-        __syncthreads();  // A complete; every read of B by the previous realisation done
-        const AccT inv = (AccT)1 / (AccT)(it + 1);
+    // PD realisations in flight ahead of the pass being transformed
+    constexpr int PD = RB == 1 ? 3 : 4;
+    VA pf[PD];
+    if (count > 0) {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) pf[k] = fetch(k);
+    }
+    for (int i0 = 0; i0 < count; i0 += RB) {
+        VA prev[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) prev[t] = pf[t];
+#pragma unroll
+        for (int k = 0; k + RB < PD; ++k) pf[k] = pf[k + RB];
+#pragma unroll
+        for (int k = PD - RB; k < PD; ++k) pf[k] = fetch(i0 + k + RB);
+#pragma unroll
+        for (int t = 0; t < RB; ++t) vstore<T, G>(A + t * TS + own, prev[t]);
+        __syncthreads();  // A complete; every read of B by the previous pass done
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int d = 1 << s;  // dilation in sub-grid units
-            const T* ra = A + yo * RS;
-            VA o;
-            if (2 * d <= G) {  // the five taps of the G outputs lie in three vectors
-                const VA l = vload<T, G>(ra + ((xo - G) & (M - 1))), c = vload<T, G>(ra + xo),
-                         r = vload<T, G>(ra + ((xo + G) & (M - 1)));
-                T w[3 * G];
 #pragma unroll
-                for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = r.e[k]; }
+            for (int t = 0; t < RB; ++t) {
+                const T* ra = A + t * TS + yo * RS;
+                VA o;
+                if (2 * d <= G) {  // the five taps of the G outputs lie in three vectors
+                    const VA l = vload<T, G>(ra + ((xo - G) & (M - 1))), c = vload<T, G>(ra + xo),
+                             r = vload<T, G>(ra + ((xo + G) & (M - 1)));
+                    T w[3 * G];
 #pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    const int b = G + k;
-                    o.e[k] = d == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
-                                    : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
-                                                 w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
+                    for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = r.e[k]; }
+#pragma unroll
+                    for (int k = 0; k < G; ++k) {
+                        const int b = G + k;
+                        o.e[k] = d == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
+                                        : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
+                                                     w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
+                    }
+                } else {  // the dilation is a multiple of the vector width
+                    o = vcombine<T, G>(vload<T, G>(ra + ((xo - 2 * d) & (M - 1))), vload<T, G>(ra + ((xo - d) & (M - 1))),
+                                       vload<T, G>(ra + xo), vload<T, G>(ra + ((xo + d) & (M - 1))),
+                                       vload<T, G>(ra + ((xo + 2 * d) & (M - 1))));
                 }
-            } else {  // the dilation is a multiple of the vector width
-                o = vcombine<T, G>(vload<T, G>(ra + ((xo - 2 * d) & (M - 1))), vload<T, G>(ra + ((xo - d) & (M - 1))),
-                                   vload<T, G>(ra + xo), vload<T, G>(ra + ((xo + d) & (M - 1))),
-                                   vload<T, G>(ra + ((xo + 2 * d) & (M - 1))));
+                vstore<T, G>(B + t * TS + own, o);
             }
-            vstore<T, G>(B + own, o);
             __syncthreads();  // B complete
-            const VA c = vcombine<T, G>(vload<T, G>(B + ((yo - 2 * d) & (M - 1)) * RS + xo),
-                                        vload<T, G>(B + ((yo - d) & (M - 1)) * RS + xo),
-                                        vload<T, G>(B + yo * RS + xo),
-                                        vload<T, G>(B + ((yo + d) & (M - 1)) * RS + xo),
-                                        vload<T, G>(B + ((yo + 2 * d) & (M - 1)) * RS + xo));
+            // realisations in order, so the Welford sequence matches one at a time
+            const AccT inv_base = (AccT)(i0 + 1);
 #pragma unroll
-            for (int cc = 0; cc < G; ++cc) {
-                const AccT x = (AccT)(prev.e[cc] - c.e[cc]);
-                const AccT dd = x - mean[s][cc];
-                mean[s][cc] = fma(dd, inv, mean[s][cc]);
-                m2[s][cc] = fma(dd, x - mean[s][cc], m2[s][cc]);
+            for (int t = 0; t < RB; ++t) {
+                const T* cb = B + t * TS + xo;
+                const VA c = vcombine<T, G>(vload<T, G>(cb + ((yo - 2 * d) & (M - 1)) * RS),
+                                            vload<T, G>(cb + ((yo - d) & (M - 1)) * RS),
+                                            vload<T, G>(cb + yo * RS),
+                                            vload<T, G>(cb + ((yo + d) & (M - 1)) * RS),
+                                            vload<T, G>(cb + ((yo + 2 * d) & (M - 1)) * RS));
+                if (RB == 1 || i0 + t < count) {
+                    const AccT inv = (AccT)1 / (inv_base + (AccT)t);
+#pragma unroll
+                    for (int cc = 0; cc < G; ++cc) {
+                        const AccT x = (AccT)(prev[t].e[cc] - c.e[cc]);
+                        const AccT dd = x - mean[s][cc];
+                        mean[s][cc] = fma(dd, inv, mean[s][cc]);
+                        m2[s][cc] = fma(dd, x - mean[s][cc], m2[s][cc]);
+                    }
+                }
+                prev[t] = c;
+                if (s + 1 < NS) vstore<T, G>(A + t * TS + own, c);  // A's row-pass reads ended at the barrier
             }
-            prev = c;
-            if (s + 1 < NS) {
-                vstore<T, G>(A + own, c);  // every row-pass read of A was before the last barrier
-                __syncthreads();           // A complete; every read of B done
-            }
+            if (s + 1 < NS) __syncthreads();  // A complete; every read of B done
         }
     }
     // merge into the running totals, or leave partials per group
@@ -1079,15 +1101,38 @@ static bool subgrid_ok(int n, int j0, int J) {
     return m >= 16 && m <= (sizeof(T) == 4 ? 64 : 32);
 }
 
+// LDS of a sub-grid stage: RB tiles of m rows of m + G values, twice.
+template <typename T>
+constexpr size_t subgrid_lds_bytes(int logm, int rb) {
+    return 2 * (size_t)rb * (1 << logm) * ((1 << logm) + Vec<T>::G) * sizeof(T);
+}
+
 template <typename T, int LOGM, int NS>
 static hipError_t launch_subgrid_nsm(const NoiseSubArgs<T>& a, int tiles, hipStream_t s) {
     constexpr int NT = (1 << (2 * LOGM)) / Vec<T>::G;
+    if (a.rb != 1 && a.rb != 2) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_starlet_noise_subgrid<T, LOGM, NS, 1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_starlet_noise_subgrid<T, LOGM, NS, 2>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const size_t lds = subgrid_lds_bytes<T>(LOGM, a.rb);
+    if (lds > (size_t)kLdsBytes) return hipErrorInvalidConfiguration;
     static const char* names[12] = {"noise_stage_j1", "noise_stage_j2", "noise_stage_j3",
                                     "noise_stage_j4", "noise_stage_j5", "noise_stage_j6",
                                     "noise_stage_j7", "noise_stage_j8", "noise_stage_j9",
                                     "noise_stage_j10", "noise_stage_j11", "noise_stage_j12"};
-    AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
-                k_starlet_noise_subgrid<T, LOGM, NS><<<dim3(tiles, a.groups), NT, 0, s>>>(a));
+    if (a.rb == 2)
+        AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                    k_starlet_noise_subgrid<T, LOGM, NS, 2><<<dim3(tiles, a.groups), NT, lds, s>>>(a));
+    else
+        AMAP_LAUNCH(names[a.j0 - 1 < 12 ? a.j0 - 1 : 11], s,
+                    k_starlet_noise_subgrid<T, LOGM, NS, 1><<<dim3(tiles, a.groups), NT, lds, s>>>(a));
     return hipGetLastError();
 }
 
@@ -1182,7 +1227,7 @@ bool analytic_subgrid_plan(int n, int J, StagePlan* out) {
         out->st[out->nstages++] = StagePlan::Stage{j0, g.ns, g.tw, g.th, g.rb, 0};
         j0 += g.ns;
     }
-    out->st[out->nstages++] = StagePlan::Stage{js, J - js, n >> (js - 1), n >> (js - 1), 1, 1};
+    out->st[out->nstages++] = StagePlan::Stage{js, J - js, n >> (js - 1), n >> (js - 1), 2, 1};
     return true;
 }
 template bool analytic_subgrid_plan<float>(int, int, StagePlan*);
@@ -1206,8 +1251,10 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             const StagePlan::Stage& t = a.plan->st[k];
             StageGeom g{};
             if (t.sub) {  // a final noise stage on whole sub-grids
-                if (!acc || k + 1 != a.plan->nstages || t.j0 + t.ns != a.J || !subgrid_ok<T>(n, t.j0, a.J))
+                if (!acc || k + 1 != a.plan->nstages || t.j0 + t.ns != a.J || !subgrid_ok<T>(n, t.j0, a.J) ||
+                    (t.rb != 1 && t.rb != 2))
                     return hipErrorInvalidValue;
+                g.rb = t.rb;
                 plan[nstages++] = Stage{t.j0, t.ns, g, false, true};
                 continue;
             }
@@ -1277,7 +1324,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             int logm = 0;
             while ((1 << logm) < n / d0) ++logm;
             NoiseSubArgs<T> s;
-            s.logn = a.logn; s.j0 = st.j0; s.src = cur; s.batch = a.batch;
+            s.logn = a.logn; s.j0 = st.j0; s.src = cur; s.batch = a.batch; s.rb = st.g.rb;
             s.groups = noise_groups(tiles, a.batch); s.done = a.done;
             s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
             s.part = a.part;
@@ -1455,12 +1502,12 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
                 }
             }
         }
-        if (acc && e == hipSuccess && subgrid_ok<T>(n, j, J)) {
+        for (int rb = 1; rb <= 2 && acc && e == hipSuccess && subgrid_ok<T>(n, j, J); ++rb) {
             // all remaining scales on whole sub-grids (a final stage)
             const int m = n >> (j - 1);
             StagePlan sub;
             sub.nstages = 1;
-            sub.st[0] = StagePlan::Stage{j, J - j, m, m, 1, 1};
+            sub.st[0] = StagePlan::Stage{j, J - j, m, m, rb, 1};
             StarletArgs<T> b = a;
             b.plan = &sub;
             e = launch_starlet<T>(b);  // warm
@@ -1472,8 +1519,8 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess) {
                 if (tune_log())
-                    std::fprintf(stderr, "amap tune: n=%d J=%d noise batch=%d stage j0=%d ns=%d sub-grids %dx%d: %.1f us\n",
-                                 n, J, a.batch, j, J - j, m, m, 1e3f * ms / reps);
+                    std::fprintf(stderr, "amap tune: n=%d J=%d noise batch=%d stage j0=%d ns=%d sub-grids %dx%d rb=%d: %.1f us\n",
+                                 n, J, a.batch, j, J - j, m, m, rb, 1e3f * ms / reps);
                 const float t = ms / reps;
                 if (best[j] < 0.f || t < best[j]) {
                     best[j] = t;
