@@ -420,20 +420,26 @@ __device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int 
         for (int n2 = 0; n2 < N2; ++n2) b[r][n2] = E[(t + N2 * r) * (N2 + 1) + n2];
         dft_reg<T, N2, false>(b[r]);
     }
-    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2);
-    // the integer numerators and denominator are exact in T (|m| <= n/2)
+    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2).
+    // Every integer here is exact in T (|m| <= n/2, so m1^2 + m2^2 < 2^24),
+    // so the arithmetic runs in T without integer multiplies; 1 / max(den, 1)
+    // gives D(0) = 0 because both numerators vanish there.  The imaginary
+    // part is 0 on the Nyquist row and column.
     const T inv_n2 = (T)1 / ((T)N * (T)N);
-    const int m2 = signed_freq(y, N);
+    const int m2i = signed_freq(y, N);
+    const T m2 = (T)m2i, m2sq = m2 * m2;
+    const T two_m2 = m2i == -N / 2 ? (T)0 : (T)2 * m2;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
+        const int base = t + N2 * r;  // frequency index of k2 = 0
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            const int m1 = signed_freq(t + N2 * r + N1 * k2, N);
-            const int den = m1 * m1 + m2 * m2;
-            const bool nyq = (m1 == -N / 2) || (m2 == -N / 2);
-            const T s = den ? inv_n2 * recip((T)den) : (T)0;  // D(0) = 0
-            const T dr = (T)(m1 * m1 - m2 * m2) * s;
-            const T di = nyq ? (T)0 : (T)(2 * m1 * m2) * s;
+            const int i1 = base + N1 * k2;
+            const T m1 = (T)(i1 < N / 2 ? i1 : i1 - N);
+            const T m1sq = m1 * m1;
+            const T s = inv_n2 * recip(fmax(m1sq + m2sq, (T)1));
+            const T dr = (m1sq - m2sq) * s;
+            const T di = i1 == N / 2 ? (T)0 : (m1 * two_m2) * s;
             const cpx<T> v = b[r][k2];
             b[r][k2] = make_cpx(v.x * dr + v.y * di, v.y * dr - v.x * di);
         }
