@@ -191,38 +191,47 @@ __device__ __forceinline__ void row_pass(const T* A, T* Bf, int RS, int dx, int 
                                          float inv_nv, int rtot, int vlo, int tstride) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
-    // RB tiles share each pass: item e of tile t is e + t * rtot
-    for (int e0 = threadIdx.x; e0 < RB * rtot; e0 += U * NT) {
+    // one item: output vector e of the RB tiles' rows (item e of tile t is
+    // e + t * rtot), returned with its offset in B
+    auto item = [&](int e, VA& o) {
+        int tb = 0;
+        if (RB > 1 && e >= rtot) { e -= rtot; tb = tstride; }
+        const int r = fdiv(e, inv_nv);
+        const int i0 = rlo4 + (e - r * nv) * G;
+        const int ro = tb + (vlo + r) * RS;
+        const T* ra = A + ro;
+        if constexpr (DXC != 0) {
+            const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0), rr = vload<T, G>(ra + i0 + G);
+            T w[3 * G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
+                o.e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
+            }
+        } else {
+            o = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
+                               vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
+                               vload<T, G>(ra + i0 + 2 * dx));
+        }
+        return ro + i0;
+    };
+    const int total = RB * rtot;
+    for (int e0 = threadIdx.x; e0 < total; e0 += U * NT) {
         VA o[U];
         int off[U];
+        if (e0 + (U - 1) * NT < total) {  // all U items exist: no guards
+#pragma unroll
+            for (int u = 0; u < U; ++u) off[u] = item(e0 + u * NT, o[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) vstore<T, G>(Bf + off[u], o[u]);
+            continue;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int e = e0 + u * NT;
-            off[u] = -1;
-            if (e < RB * rtot) {
-                int tb = 0;
-                if (RB > 1 && e >= rtot) { e -= rtot; tb = tstride; }
-                const int r = fdiv(e, inv_nv);
-                const int i0 = rlo4 + (e - r * nv) * G;
-                const T* ra = A + tb + (vlo + r) * RS;
-                off[u] = tb + (vlo + r) * RS + i0;
-                if constexpr (DXC != 0) {
-                    const VA l = vload<T, G>(ra + i0 - G), c = vload<T, G>(ra + i0),
-                             rr = vload<T, G>(ra + i0 + G);
-                    T w[3 * G];
-#pragma unroll
-                    for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
-#pragma unroll
-                    for (int k = 0; k < G; ++k) {
-                        const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
-                        o[u].e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
-                    }
-                } else {
-                    o[u] = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
-                                          vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
-                                          vload<T, G>(ra + i0 + 2 * dx));
-                }
-            }
+            const int e = e0 + u * NT;
+            off[u] = e < total ? item(e, o[u]) : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -276,6 +285,18 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
         if (vfirst >= chi) continue;
         const T* col = Bf + tb + i0;
         VA win[kSegLen + 4];
+        if (vfirst + dv * (kSegLen - 1) < chi) {
+            // a whole segment: every tap row lies below chi + 2 dv, no guards
+            const int step = dv * RS;
+            const T* wp = col + (vfirst - 2 * dv) * RS;
+#pragma unroll
+            for (int k = 0; k < kSegLen + 4; ++k) win[k] = vload<T, G>(wp + k * step);
+            T* op = A + tb + vfirst * RS + i0;
+#pragma unroll
+            for (int k = 0; k < kSegLen; ++k)
+                vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < kSegLen + 4; ++k) {
             const int v = vfirst + dv * (k - 2);
