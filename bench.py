@@ -39,6 +39,9 @@ FP32_PEAK_TFLOPS = 157.3
 
 N, J, R_REAL, SEED, THRESH = 1024, 7, 256, 23, 3.0
 TRAFFIC_PROFILE = "noise_path_1024_J7_R256_traffic.md"
+# tuned stage schedules of the bench's shapes, loaded instead of tuning live
+# (so that its kernels are exactly those of the committed profiles)
+SCHEDULES = "noise_path_1024_J7_R256_schedules.json"
 GRF_SEED, NOISE_SEED = 11, 12
 
 
@@ -310,6 +313,11 @@ def main():
                     help="skip the uneven-batch and served-stream measurements (profiler runs)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of each served-stream level")
+    ap.add_argument("--schedules", default=os.path.join(ROOT, "profiles", SCHEDULES),
+                    help="JSON of tile schedules to load (amap_plans_load) instead of tuning; "
+                         "'none' tunes live")
+    ap.add_argument("--save-schedules", default=None,
+                    help="write the context's schedules (amap_plans_read) to this file at the end")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -330,6 +338,11 @@ def main():
     t1 = torch.tensor(g1, dtype=torch.float32, device=dev)
     t2 = torch.tensor(g2, dtype=torch.float32, device=dev)
     ctx = amap.Context(0)
+    schedules_source = "tuned live"
+    if args.schedules and args.schedules != "none" and os.path.exists(args.schedules):
+        with open(args.schedules) as f:
+            ctx.plans_load(f.read())
+        schedules_source = os.path.relpath(args.schedules, ROOT)
     out = {
         "kappa_e": torch.empty((N, N), dtype=torch.float32, device=dev),
         "planes": torch.empty((J, N, N), dtype=torch.float32, device=dev),
@@ -502,7 +515,11 @@ def main():
         # tile schedules the autotuner chose for this run: [j0, scales, tile
         # width, tile sub-rows, realisations per LDS pass] per stage
         "schedules": ctx.plans(),
+        "schedules_source": schedules_source,
     }
+    if args.save_schedules:
+        with open(args.save_schedules, "w") as f:
+            json.dump(ctx.plans(), f)
     ctx.close()
     if args.cpu_seconds > 0:
         print("bench: cpu baseline (oracle, ~%.0f s)" % args.cpu_seconds, file=sys.stderr,

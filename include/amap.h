@@ -113,6 +113,16 @@ amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
  * AMAP_E_INVAL if it does not fit. */
 amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);
 
+/* Loads schedules in amap_plans_read's format (NUL-terminated JSON) into the
+ * context, replacing any it holds for the same shapes; later transforms of
+ * those shapes use them instead of tuning (mode 1) or of the mode-2
+ * analytic schedule.  Lets a caller keep tuned schedules across processes
+ * and run a fixed schedule (for instance under a profiler, whose timing
+ * would steer the tuner).  Every schedule is checked against the planner's
+ * tiles and the stage rules first; AMAP_E_INVAL (nothing loaded) if one is
+ * malformed or invalid. */
+amap_status amap_plans_load(amap_ctx_t ctx, const char* json);
+
 /* Per-kernel timing (diagnostics): while enabled, every kernel the context
  * launches is bracketed by two HIP events recorded on the launch's stream.
  * Work captured into a batch plan's graph is not timed. */

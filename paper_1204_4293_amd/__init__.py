@@ -71,6 +71,7 @@ def load():
         "amap_timing_enable": (I, [P, I]),
         "amap_set_autotune": (I, [P, I]),
         "amap_plans_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
+        "amap_plans_load": (I, [P, ctypes.c_char_p]),
         "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
         "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
@@ -178,6 +179,12 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 18)
         _check(load().amap_plans_read(self._h, buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    def plans_load(self, plans):
+        """Load schedules (a list of dicts as returned by plans(), or its JSON)."""
+        import json
+        text = plans if isinstance(plans, str) else json.dumps(plans)
+        _check(load().amap_plans_load(self._h, text.encode()))
 
     def set_autotune(self, enable=True):
         """True/1: tuned schedules; False/0: analytic planner; 2: analytic

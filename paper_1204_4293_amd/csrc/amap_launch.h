@@ -110,6 +110,8 @@ template <typename T> hipError_t launch_starlet(const StarletArgs<T>& a);
 template <typename T> bool starlet_all_tiled(int n, int J);
 // The analytic noise schedule ending in a sub-grid final stage, if one applies.
 template <typename T> bool analytic_subgrid_plan(int n, int J, StagePlan* out);
+// Whether a schedule is one launch_starlet accepts for this shape.
+template <typename T> bool plan_valid(int n, int J, bool noise, const StagePlan& plan);
 template <typename T>
 hipError_t launch_peak_hist(int logn, int nplanes, const T* planes, int sign, double lo,
                             double width, int nbins, long long* hist, hipStream_t s);

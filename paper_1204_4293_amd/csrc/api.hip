@@ -475,6 +475,79 @@ amap_status amap_timing_enable(amap_ctx_t c, int enable) {
     return AMAP_OK;
 }
 
+// Reads the next integer after the quoted key (a key of amap_plans_read's
+// format) at or after *p; advances *p past it.
+static bool json_int(const char** p, const char* key, long* out) {
+    const char* k = std::strstr(*p, key);
+    if (!k) return false;
+    const char* q = k + std::strlen(key);
+    while (*q == ' ' || *q == ':' || *q == '"') ++q;
+    char* end = nullptr;
+    const long v = std::strtol(q, &end, 10);
+    if (end == q) return false;
+    *out = v;
+    *p = end;
+    return true;
+}
+
+amap_status amap_plans_load(amap_ctx_t c, const char* json) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (!json) return fail(AMAP_E_INVAL, "json must not be NULL");
+    struct Entry { int mode; std::array<int, 5> key; StagePlan plan; };
+    std::vector<Entry> got;
+    const char* p = json;
+    int idx = 0;
+    while ((p = std::strchr(p, '{')) != nullptr) {
+        long v[6];
+        const char* keys[6] = {"\"mode\"", "\"elem\"", "\"logn\"", "\"J\"", "\"noise\"", "\"batch\""};
+        for (int i = 0; i < 6; ++i)
+            if (!json_int(&p, keys[i], &v[i])) return fail(AMAP_E_INVAL, "schedule %d: missing %s", idx, keys[i]);
+        const char* st = std::strstr(p, "\"stages\"");
+        if (!st) return fail(AMAP_E_INVAL, "schedule %d: missing \"stages\"", idx);
+        st = std::strchr(st, '[');
+        if (!st) return fail(AMAP_E_INVAL, "schedule %d: malformed stages", idx);
+        ++st;
+        Entry e;
+        e.mode = (int)v[0];
+        e.key = {(int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]};
+        e.plan.nstages = 0;
+        // stages: [[j0, ns, tw, th, rb, sub], ...] up to the closing bracket
+        while (true) {
+            while (*st == ' ' || *st == ',') ++st;
+            if (*st == ']') { ++st; break; }
+            if (*st != '[' || e.plan.nstages >= 16) return fail(AMAP_E_INVAL, "schedule %d: malformed stages", idx);
+            ++st;
+            long f[6];
+            for (int i = 0; i < 6; ++i) {
+                while (*st == ' ' || *st == ',') ++st;
+                char* end = nullptr;
+                f[i] = std::strtol(st, &end, 10);
+                if (end == st) return fail(AMAP_E_INVAL, "schedule %d: stage with fewer than 6 fields", idx);
+                st = end;
+            }
+            while (*st == ' ') ++st;
+            if (*st != ']') return fail(AMAP_E_INVAL, "schedule %d: stage with more than 6 fields", idx);
+            ++st;
+            e.plan.st[e.plan.nstages++] = StagePlan::Stage{(int)f[0], (int)f[1], (int)f[2], (int)f[3], (int)f[4], (int)f[5]};
+        }
+        p = st;
+        const int elem = e.key[0], logn = e.key[1], J = e.key[2], noise = e.key[3], batch = e.key[4];
+        if ((e.mode != 1 && e.mode != 2) || (elem != 4 && elem != 8) || logn < 4 || logn > kMaxLogN ||
+            J < 2 || (1 << J) > (1 << logn) || (noise != 0 && noise != 1) || batch < 1)
+            return fail(AMAP_E_INVAL, "schedule %d: bad mode, element size, size, J, noise flag or batch", idx);
+        if (e.plan.nstages > 0) {
+            const bool ok = elem == 4 ? plan_valid<float>(1 << logn, J, noise != 0, e.plan)
+                                      : plan_valid<double>(1 << logn, J, noise != 0, e.plan);
+            if (!ok) return fail(AMAP_E_INVAL, "schedule %d: not a valid stage schedule for n = %d, J = %d", idx, 1 << logn, J);
+        }
+        got.push_back(e);
+        ++idx;
+    }
+    for (const Entry& e : got) (e.mode == 1 ? c->plans : c->plans_sub)[e.key] = e.plan;
+    return AMAP_OK;
+}
+
 amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
     g_last_error.clear();
     if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");

@@ -1254,6 +1254,32 @@ bool analytic_subgrid_plan(int n, int J, StagePlan* out) {
 template bool analytic_subgrid_plan<float>(int, int, StagePlan*);
 template bool analytic_subgrid_plan<double>(int, int, StagePlan*);
 
+// True if plan is a schedule launch_starlet accepts for an n x n, J-plane
+// transform (noise statistics or plane output): consecutive stages from
+// scale 1 to J-1, each with a tile the planner offers for its start and
+// scale count (or, last and for noise only, a valid sub-grid stage).
+template <typename T>
+bool plan_valid(int n, int J, bool noise, const StagePlan& plan) {
+    if (plan.nstages < 1 || plan.nstages > 16) return false;
+    int j = 1;
+    for (int k = 0; k < plan.nstages; ++k) {
+        const StagePlan::Stage& t = plan.st[k];
+        if (t.j0 != j || t.ns < 1 || t.j0 + t.ns > J) return false;
+        if (t.sub) {
+            if (!noise || k + 1 != plan.nstages || t.j0 + t.ns != J || !subgrid_ok<T>(n, t.j0, J) ||
+                (t.rb != 1 && t.rb != 2) || t.tw != (n >> (t.j0 - 1)) || t.th != t.tw)
+                return false;
+        } else {
+            StageGeom g{};
+            if (t.ns > 3 || !stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, noise, &g)) return false;
+        }
+        j += t.ns;
+    }
+    return j == J;
+}
+template bool plan_valid<float>(int, int, bool, const StagePlan&);
+template bool plan_valid<double>(int, int, bool, const StagePlan&);
+
 template bool starlet_all_tiled<float>(int, int);
 template bool starlet_all_tiled<double>(int, int);
 

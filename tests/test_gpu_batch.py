@@ -186,3 +186,31 @@ def test_autotuned_schedule_matches_analytic(ctx, n, J):
         torch.cuda.synchronize()
         assert float((sa.double() - sb.double()).abs().max()) <= 1e-6 * float(sb.double().abs().max())
     plain.close()
+
+
+def test_schedules_round_trip_and_validation(ctx):
+    # schedules read from one context and loaded into another reproduce its
+    # results bit for bit; invalid schedules are refused and load nothing
+    n, J, R, seed = 256, 6, 12, 5
+    _, g1, g2 = S.shear_map(n, 61, 62)
+    t1, t2 = dev(g1, torch.float32), dev(g2, torch.float32)
+    sa, _ = ctx.noise_maps(t1, t2, J, R, seed, want_snr=False)
+    plans = [p for p in ctx.plans() if p["logn"] == 8 and p["J"] == J]
+    assert plans and any(p["noise"] for p in plans)
+    other = amap.Context(0)
+    other.plans_load(plans)
+    got = [p for p in other.plans() if p["logn"] == 8 and p["J"] == J]
+    assert sorted(map(str, got)) == sorted(map(str, plans))
+    sb, _ = other.noise_maps(t1, t2, J, R, seed, want_snr=False)
+    torch.cuda.synchronize()
+    assert torch.equal(sa, sb)
+    before = other.plans()
+    bad = [dict(plans[0]), ]
+    bad[0]["stages"] = [list(st) for st in plans[0]["stages"]]
+    bad[0]["stages"][0][2] = 48                      # no such tile width
+    for broken in (bad, '[{"mode": 1, "elem": 4}]', '[{"mode": 1, "elem": 4, "logn": 8, "J": 6, '
+                   '"noise": 1, "batch": 12, "stages": [[1, 2, 64, 32, 1, 0], [4, 2, 64, 32, 1, 0]]}]'):
+        with pytest.raises(amap.AmapError):
+            other.plans_load(broken)
+    assert other.plans() == before
+    other.close()
