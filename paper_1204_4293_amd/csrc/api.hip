@@ -386,8 +386,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
     t.planes = nullptr; t.planes_stride = 0; t.cbuf0 = cb0; t.cbuf1 = cb1; t.tmp = tmp;
     t.wbuf = wb; t.M = M; t.M2 = M2; t.part = part; t.stream = s;
     const StagePlan* plan = tuned_plan<T>(ctx, t);
-    AMAP_HIP(launch_zero_f64(M, (long long)(J - 1) * n2, s), "zero accumulators");
-    AMAP_HIP(launch_zero_f64(M2, (long long)(J - 1) * n2, s), "zero accumulators");
+    // M and M2 need no clearing: the first batch's merges write them unread
     for (int r0 = 0; r0 < n_real; r0 += B) {
         const int bb = (n_real - r0) < B ? (n_real - r0) : B;
         AMAP_TRY(enqueue_ks<T>(ctx, logn, bb, g1, g2, 0, C, kap, nullptr, n2, true, seed,

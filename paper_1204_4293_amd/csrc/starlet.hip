@@ -615,8 +615,13 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
             for (int s = 0; s < NS; ++s)
 #pragma unroll
                 for (int h = 0; h < G / 2; ++h) {
-                    mo[s][h] = *reinterpret_cast<const double2*>(Mp + s * n2 + base + 2 * h);
-                    qo[s][h] = *reinterpret_cast<const double2*>(Qp + s * n2 + base + 2 * h);
+                    if (a.done == 0) {  // the first batch: nothing merged yet, M and M2 unread
+                        mo[s][h] = make_double2(0.0, 0.0);
+                        qo[s][h] = make_double2(0.0, 0.0);
+                    } else {
+                        mo[s][h] = *reinterpret_cast<const double2*>(Mp + s * n2 + base + 2 * h);
+                        qo[s][h] = *reinterpret_cast<const double2*>(Qp + s * n2 + base + 2 * h);
+                    }
                 }
 #pragma unroll
             for (int s = 0; s < NS; ++s)
@@ -779,7 +784,10 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int c = 0; c < G; ++c) { mo[s][c] = Mp[s * n2 + gown + c]; qo[s][c] = Qp[s * n2 + gown + c]; }
+            for (int c = 0; c < G; ++c) {
+                mo[s][c] = a.done == 0 ? 0.0 : Mp[s * n2 + gown + c];  // the first batch: unread
+                qo[s][c] = a.done == 0 ? 0.0 : Qp[s * n2 + gown + c];
+            }
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -810,7 +818,8 @@ k_merge_partials(const P* __restrict__ part, int groups, int ns, int batch, int 
     if (idx >= n2) return;
     for (int s = 0; s < ns; ++s) {
         double na = (double)done;
-        double mean = M[(long long)s * n2 + idx], m2 = M2[(long long)s * n2 + idx];
+        double mean = done == 0 ? 0.0 : M[(long long)s * n2 + idx];  // the first batch: unread
+        double m2 = done == 0 ? 0.0 : M2[(long long)s * n2 + idx];
         for (int grp = 0; grp < groups; ++grp) {
             const double nb = (double)((batch - grp + groups - 1) / groups);
             if (nb == 0.0) continue;
@@ -849,9 +858,10 @@ k_welford_merge(const T* __restrict__ w, long long w_map_stride, int ns, int bat
             m2 += d * (v - mean);
         }
         const long long e = (long long)s * n2 + idx;
-        const double delta = mean - M[e];
-        M[e] += delta * (nb / nt);
-        M2[e] += m2 + delta * delta * (na * nb / nt);
+        const double mo = done == 0 ? 0.0 : M[e], qo = done == 0 ? 0.0 : M2[e];  // the first batch: unread
+        const double delta = mean - mo;
+        M[e] = mo + delta * (nb / nt);
+        M2[e] = qo + (m2 + delta * delta * (na * nb / nt));
     }
 }
 

@@ -36,35 +36,58 @@ __global__ void k_zero_i64(long long* p, long long count) {
     if (i < count) p[i] = 0;
 }
 
-// Strict 8-neighbour maxima above thr, periodic.  grid (n*n/256, nplanes).
-// One atomic add per wavefront of the ballot's population count.
+// Strict 8-neighbour maxima above thr, periodic.  grid (n*n/1024, nplanes):
+// each thread tests four consecutive pixels of a row (n >= 16, so they share
+// the row) and loads their neighbourhood only if one of them is above thr.
+// One atomic add per wavefront of its count (summed over three ballots of
+// the per-thread counts' bits).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_count_peaks(const T* __restrict__ snr, int logn, double thr, long long* __restrict__ counts) {
     const int n = 1 << logn, m = n - 1;
     const long long n2 = (long long)n * n;
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    bool peak = false;
+    const long long idx = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;  // the first pixel
+    int npk = 0;
     if (idx < n2) {
         const T* p = snr + (long long)blockIdx.y * n2;
         const int x = (int)(idx & m), y = (int)(idx >> logn);
-        const T v = p[idx];
-        peak = (double)v > thr;
-        if (peak) {
+        T r[3][6];  // rows y-1, y, y+1 at columns x-1 .. x+4
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[1][1 + i] = p[idx + i];
+        bool cand[4], any = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            cand[i] = (double)r[1][1 + i] > thr;
+            any = any || cand[i];
+        }
+        if (any) {
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
-                const long long row = (long long)((y + dy) & m) * n;
+                const T* row = p + (long long)((y + dy) & m) * n;
+                r[dy + 1][0] = row[(x - 1) & m];
+                r[dy + 1][5] = row[(x + 4) & m];
+                if (dy != 0) {
 #pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (dy == 0 && dx == 0) continue;
-                    peak = peak && (v > p[row + ((x + dx) & m)]);
+                    for (int i = 0; i < 4; ++i) r[dy + 1][1 + i] = row[x + i];
                 }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T v = r[1][1 + i];
+                bool pk = cand[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        if (a != 1 || b != 1) pk = pk & (v > r[a][i + b]);
+                npk += pk ? 1 : 0;
             }
         }
     }
-    const unsigned long long mask = __ballot(peak);
-    if ((threadIdx.x & 63) == 0 && mask)
-        atomicAdd((unsigned long long*)&counts[blockIdx.y], (unsigned long long)__popcll(mask));
+    const unsigned long long total = (unsigned long long)__popcll(__ballot(npk & 1)) +
+                                     2ull * __popcll(__ballot(npk & 2)) + 4ull * __popcll(__ballot(npk & 4));
+    if ((threadIdx.x & 63) == 0 && total)
+        atomicAdd((unsigned long long*)&counts[blockIdx.y], total);
 }
 
 // Histogram of peak heights (Sec. 2.2): pixels that are strict 8-neighbour
@@ -86,17 +109,19 @@ k_peak_hist(const T* __restrict__ planes, int logn, int sign, double lo, double 
         const T* p = planes + (long long)blockIdx.y * n2;
         const int x = (int)(idx & m), y = (int)(idx >> logn);
         const T h = sign > 0 ? p[idx] : -p[idx];
-        bool peak = true;
+        // the eight neighbour loads issue together, then one test
+        T q[8];
+        int k = 0;
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
             const long long row = (long long)((y + dy) & m) * n;
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dy == 0 && dx == 0) continue;
-                const T q = p[row + ((x + dx) & m)];
-                peak = peak && (h > (sign > 0 ? q : -q));
-            }
+            for (int dx = -1; dx <= 1; ++dx)
+                if (dy != 0 || dx != 0) q[k++] = p[row + ((x + dx) & m)];
         }
+        bool peak = true;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) peak = peak & (h > (sign > 0 ? q[i] : -q[i]));
         if (peak) {
             const double b = floor(((double)h - lo) / width);
             if (b >= 0.0 && b < (double)nbins) atomicAdd(&bins[(int)b], 1u);
@@ -219,7 +244,7 @@ hipError_t launch_count_peaks(int logn, int nplanes, const T* snr, double thr, l
     hipError_t e = launch_zero_i64(counts, nplanes, s);
     if (e != hipSuccess) return e;
     AMAP_LAUNCH("count_peaks", s,
-                k_count_peaks<T><<<dim3(blocks_for(n2), nplanes), 256, 0, s>>>(snr, logn, thr,
+                k_count_peaks<T><<<dim3(blocks_for(n2 / 4), nplanes), 256, 0, s>>>(snr, logn, thr,
                                                                                counts));
     return hipGetLastError();
 }
