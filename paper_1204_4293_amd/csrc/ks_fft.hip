@@ -394,15 +394,16 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
 }
 
 // ---- P2: rows: forward FFT along x, multiply by conj(D)/n^2, inverse (four-step) -
-// The work of one spectral row y for the N2 lanes t of a line, with E its
-// exchange region: on return a[n] holds the row's inverse transform at
-// x = t + N2 n.
-template <typename T, int LOGN>
-__device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int y, int t,
-                                            cpx<T>* E, const cpx<T>* __restrict__ tw,
-                                            cpx<T> (&a)[FS<LOGN>::N1]) {
+// The forward half of one spectral row y for the N2 lanes t of a line, with
+// E its exchange region: on return b[r][k2] holds the row's transform times
+// SCALE conj(D)/n^2 at frequency k1 + N1 k2, k1 = t + N2 r.
+template <typename T, int LOGN, int SCALE_DEN = 1>
+__device__ __forceinline__ void ks_row_forward(const cpx<T>* __restrict__ row, int y, int t,
+                                               cpx<T>* E, const cpx<T>* __restrict__ tw,
+                                               cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2]) {
     using F = FS<LOGN>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR;
+    cpx<T> a[N1];
     // forward, step 1: DFT_N1 over n1 of x[N2 n1 + t]
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = row[N2 * n1 + t];
@@ -413,7 +414,6 @@ __device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int 
     });
     wave_lds_sync();
     // forward, step 2: DFT_N2 over n2 -> X[k1 + N1 k2], k1 = t + N2 r
-    cpx<T> b[RR][N2];
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
 #pragma unroll
@@ -424,27 +424,39 @@ __device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int 
     // Every integer here is exact in T (|m| <= n/2, so m1^2 + m2^2 < 2^24),
     // so the arithmetic runs in T without integer multiplies; 1 / max(den, 1)
     // gives D(0) = 0 because both numerators vanish there.  The imaginary
-    // part is 0 on the Nyquist row and column.
-    const T inv_n2 = (T)1 / ((T)N * (T)N);
+    // part is 0 on the Nyquist row and column.  The frequency index is
+    // t + c with c = N2 r + N1 k2 a multiple of N2 and t < N2, so it lies
+    // below n/2 exactly when c does: m1 is t plus a constant.
+    const T scale = (T)1 / ((T)N * (T)N * (T)SCALE_DEN);
     const int m2i = signed_freq(y, N);
     const T m2 = (T)m2i, m2sq = m2 * m2;
     const T two_m2 = m2i == -N / 2 ? (T)0 : (T)2 * m2;
+    const T tf = (T)t;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
-        const int base = t + N2 * r;  // frequency index of k2 = 0
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            const int i1 = base + N1 * k2;
-            const T m1 = (T)(i1 < N / 2 ? i1 : i1 - N);
+            const int c = N2 * r + N1 * k2;
+            const T m1 = tf + (T)(c < N / 2 ? c : c - N);
             const T m1sq = m1 * m1;
-            const T s = inv_n2 * recip(fmax(m1sq + m2sq, (T)1));
+            const T s = scale * recip(fmax(m1sq + m2sq, (T)1));
             const T dr = (m1sq - m2sq) * s;
-            const T di = i1 == N / 2 ? (T)0 : (m1 * two_m2) * s;
+            const T di = (c == N / 2 && t == 0) ? (T)0 : (m1 * two_m2) * s;
             const cpx<T> v = b[r][k2];
             b[r][k2] = make_cpx(v.x * dr + v.y * di, v.y * dr - v.x * di);
         }
     }
-    wave_lds_sync();  // step-2 reads are done before the exchange is reused
+}
+
+// The inverse half: from b[r][k2] at frequency k1 + N1 k2 (k1 = t + N2 r),
+// on return a[n] holds the row's inverse transform at x = t + N2 n.
+template <typename T, int LOGN>
+__device__ __forceinline__ void ks_row_inverse(cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2], int t,
+                                               cpx<T>* E, const cpx<T>* __restrict__ tw,
+                                               cpx<T> (&a)[FS<LOGN>::N1]) {
+    using F = FS<LOGN>;
+    constexpr int N1 = F::N1, N2 = F::N2, RR = F::RR;
+    wave_lds_sync();  // earlier reads of the exchange region are done before it is reused
     // inverse, step 1: DFT_N2 over k2 for each k1 held, twiddle, exchange
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
@@ -460,6 +472,16 @@ __device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int 
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) a[k1] = E[t * (N1 + 1) + k1];
     dft_reg<T, N1, true>(a);
+}
+
+// The whole row: forward, multiply, inverse.
+template <typename T, int LOGN>
+__device__ __forceinline__ void ks_row_line(const cpx<T>* __restrict__ row, int y, int t,
+                                            cpx<T>* E, const cpx<T>* __restrict__ tw,
+                                            cpx<T> (&a)[FS<LOGN>::N1]) {
+    cpx<T> b[FS<LOGN>::RR][FS<LOGN>::N2];
+    ks_row_forward<T, LOGN>(row, y, t, E, tw, b);
+    ks_row_inverse<T, LOGN>(b, t, E, tw, a);
 }
 
 template <typename T, int LOGN>
@@ -483,12 +505,17 @@ k_ks_rows(cpx<T>* __restrict__ C, const cpx<T>* __restrict__ tw) {
 // the inverse transform of the Hermitian part H(k) = [K(k) + conj(K(-k))]/2
 // of its spectrum K, which is real; two maps a, b then share one inverse
 // transform, of Z = H_a + i H_b, whose real and imaginary parts are their
-// kappa_E.  After the inverse transform along x, row y of the Hermitian
-// part is [c(y, x) + conj(c(-y, x))] / 2 with c the row's transform, so a
-// workgroup unit takes rows y and -y (rows 0 and n/2 are their own
-// partners) of both maps: four lines, one per (map, row), exchange their
-// rows through LDS and write the two rows of Z over map a's rows.  Pair p
-// holds maps 2p and 2p+1 (map 2p alone, read twice, if 2p+1 = batch).
+// kappa_E.  A workgroup unit takes spectral rows y and -y (rows 0 and n/2
+// are their own partners) of both maps: four lines, one per (map, row),
+// run the forward transform and the multiply and leave their spectral rows
+// in LDS in natural frequency order (-k is the mirrored address).  The two
+// Z rows, y and -y, are then transformed back by two lane groups of 2 N2
+// lanes each (the lanes of map a, then those of map b), so every lane does
+// the same work: within a group the low half holds the even-indexed and the
+// high half the odd-indexed inputs of each length-N2 and length-N1 DFT of
+// the four-step inverse, and one radix-2 step across the halves completes
+// them.  The group writes its Z row over map a's row.  Pair p holds maps 2p
+// and 2p+1 (map 2p alone, read twice, if 2p+1 = batch).
 template <typename T, int LOGN>
 struct RowPair {
     static constexpr int N2 = FS<LOGN>::N2, N = 1 << LOGN;
@@ -497,12 +524,89 @@ struct RowPair {
     static constexpr int NT = UNITS * 4 * N2;
 };
 
+// Exchange across the halves of a group of 2 H lanes (H a power of two, the
+// group aligned to 2 H): afterwards a low lane holds (its d, its partner's
+// d) and a high lane (its partner's s, its s) in (d, s).
+template <int H>
+__device__ __forceinline__ void half_swap_u32(uint32_t& d, uint32_t& s, bool hi) {
+    if constexpr (H == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(d, s, false, false);
+        d = r[0];
+        s = r[1];
+    } else if constexpr (H == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(d, s, false, false);
+        d = r[0];
+        s = r[1];
+    } else {
+        const uint32_t got = (uint32_t)__shfl_xor((int)(hi ? d : s), H);
+        if (hi) d = got;
+        else s = got;
+    }
+}
+template <int H, typename T>
+__device__ __forceinline__ void half_swap(T& d, T& s, bool hi) {
+    if constexpr (sizeof(T) == 4) {
+        uint32_t a = __builtin_bit_cast(uint32_t, d), b = __builtin_bit_cast(uint32_t, s);
+        half_swap_u32<H>(a, b, hi);
+        d = __builtin_bit_cast(T, a);
+        s = __builtin_bit_cast(T, b);
+    } else {
+        const uint64_t a = __builtin_bit_cast(uint64_t, d), b = __builtin_bit_cast(uint64_t, s);
+        uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+        half_swap_u32<H>(al, bl, hi);
+        half_swap_u32<H>(ah, bh, hi);
+        d = __builtin_bit_cast(T, ((uint64_t)ah << 32) | al);
+        s = __builtin_bit_cast(T, ((uint64_t)bh << 32) | bl);
+    }
+}
+
+// Radix-2 step of an inverse length-2M DFT across a lane pair, from the
+// half-length DFTs E (low lane) and O (high lane) after half_swap: the lane
+// of half h forms X[I + h M/2] = E + w O and X[I + h M/2 + M] = E - w O with
+// w = exp(2 pi i (I + h M/2) / 2M), which is i times the low lane's twiddle.
+template <typename T, int L, int I>
+__device__ __forceinline__ void pair_bfly(cpx<T>& e, cpx<T>& o, bool hi) {
+    constexpr CS w = cos_sin_2pi(I, L);
+    const T wr = hi ? (T)-w.s : (T)w.c;
+    const T wi = hi ? (T)w.c : (T)w.s;
+    const T xr = fma(wr, o.x, fma(-wi, o.y, e.x));
+    const T xi = fma(wr, o.y, fma(wi, o.x, e.y));
+    o = make_cpx<T>(fma((T)2, e.x, -xr), fma((T)2, e.y, -xi));
+    e = make_cpx<T>(xr, xi);
+}
+template <typename T, int M, int H, int... I>
+__device__ __forceinline__ void pair_bflies(cpx<T> (&v)[M], bool hi, std::integer_sequence<int, I...>) {
+    constexpr int Q = M / 2;
+    ((half_swap<H>(v[I].x, v[Q + I].x, hi), half_swap<H>(v[I].y, v[Q + I].y, hi)), ...);
+    (pair_bfly<T, 2 * M, I>(v[I], v[Q + I], hi), ...);
+}
+// Inverse DFT of length 2M over a lane pair (l, l + H): the low lane holds
+// inputs 0, 2, .., the high lane 1, 3, .. (M each, in order).  On return the
+// lane of half h holds outputs i + h M/2 in v[i] and i + h M/2 + M in
+// v[M/2 + i], i < M/2.
+template <typename T, int M, int H>
+__device__ __forceinline__ void pair_dft_inv(cpx<T> (&v)[M], bool hi) {
+    static_assert(M >= 2, "at least two values per lane");
+    dft_reg<T, M, true>(v);
+    pair_bflies<T, M, H>(v, hi, std::make_integer_sequence<int, M / 2>{});
+}
+// The output index held in v[j] by the lane of half h after pair_dft_inv.
+template <int M>
+__device__ __forceinline__ constexpr int pair_out(int j, int h) {
+    return j < M / 2 ? j + h * (M / 2) : j - M / 2 + h * (M / 2) + M;
+}
+
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((RowPair<T, LOGN>::NT))
 k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw) {
     using F = FS<LOGN>;
     using RP = RowPair<T, LOGN>;
-    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, EX = Row4<T, LOGN>::EX;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR, EX = Row4<T, LOGN>::EX;
+    constexpr int M2 = N2 / 2, M1 = N1 / 2;  // values per lane in the two inverse steps
+    // a lane group (2 N2 lanes, aligned) lies in one wavefront, so wave-level
+    // ordering covers its exchange and its cross-lane steps
+    static_assert(2 * N2 <= 64, "a lane group must lie in one wavefront");
+    static_assert(N2 >= 4, "at least two values per lane and half");
     __shared__ cpx<T> ex[RP::UNITS * 4 * EX];
     const int line = threadIdx.x / N2, t = threadIdx.x % N2;
     const int u = line >> 2, role = line & 3;  // role: map (role >> 1), row (role & 1)
@@ -510,32 +614,69 @@ k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw)
     const int r0 = q, r1 = q == 0 ? N / 2 : N - q;
     const int ma = 2 * blockIdx.y;
     const int mb = ma + 1 < batch ? ma + 1 : ma;
-    const int y = (role & 1) ? r1 : r0;
-    const cpx<T>* row = C + (long long)((role >> 1) ? mb : ma) * N * N + (long long)y * N;
-    cpx<T>* E = ex + line * EX;
-    cpx<T> a[N1];
-    ks_row_line<T, LOGN>(row, y, t, E, tw, a);
-    wave_lds_sync();
+    {
+        const int y = (role & 1) ? r1 : r0;
+        const cpx<T>* row = C + (long long)((role >> 1) ? mb : ma) * N * N + (long long)y * N;
+        cpx<T>* E = ex + line * EX;
+        cpx<T> b[RR][N2];
+        ks_row_forward<T, LOGN, 2>(row, y, t, E, tw, b);  // carries the 1/2 of H
+        wave_lds_sync();  // the forward exchange's reads are done
 #pragma unroll
-    for (int n = 0; n < N1; ++n) E[t + N2 * n] = a[n];
-    __syncthreads();  // all four rows of every unit are in LDS (and read from C)
-    // row (role & 1) of Z, half (role >> 1) of its x positions
-    const cpx<T>* base = ex + (u * 4) * EX;
-    const int self = role & 1, partner = q == 0 ? self : 1 - self;
-    const cpx<T>* caR = base + self * EX;
-    const cpx<T>* caP = base + partner * EX;
-    const cpx<T>* cbR = base + (2 + self) * EX;
-    const cpx<T>* cbP = base + (2 + partner) * EX;
-    cpx<T>* out = C + (long long)ma * N * N + (long long)y * N;
-    const T half = (T)0.5;
+        for (int r = 0; r < RR; ++r)
 #pragma unroll
-    for (int j = 0; j < N1 / 2; ++j) {
-        const int x = t + N2 * (j + (role >> 1) * (N1 / 2));
-        const cpx<T> p = caR[x], pc = caP[x], v = cbR[x], vc = cbP[x];
-        const T har = (p.x + pc.x) * half, hai = (p.y - pc.y) * half;
-        const T hbr = (v.x + vc.x) * half, hbi = (v.y - vc.y) * half;
-        out[x] = make_cpx(har - hbi, hai + hbr);
+            for (int k2 = 0; k2 < N2; ++k2) E[t + N2 * r + N1 * k2] = b[r][k2];
     }
+    // inverse: group g = role >> 1 transforms Z row y_g (slot g); h = role & 1
+    const int g = role >> 1, h = role & 1;
+    const bool hi = h != 0;
+    const int yg = g ? r1 : r0;
+    const int pg = q == 0 ? g : 1 - g;  // slot of row -y_g
+    // inter-step twiddles exp(2 pi i k1 m / N) for this lane's k1 and m
+    cpx<T> w[RR][M2];
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int j = 0; j < M2; ++j) w[r][j] = table_twiddle<T, LOGN, true>(tw, (t + N2 * r) * pair_out<M2>(j, h));
+    __syncthreads();  // the four spectral rows of every unit are in LDS (and C's rows read)
+    // Z = H_a + i H_b at k1 = t + N2 r, k2 = 2 j + h (the spectra carry the 1/2)
+    const cpx<T>* base = ex + (u * 4) * EX;
+    const cpx<T>* Ka = base + g * EX;
+    const cpx<T>* Kap = base + pg * EX;
+    const cpx<T>* Kb = base + (2 + g) * EX;
+    const cpx<T>* Kbp = base + (2 + pg) * EX;
+    cpx<T> z[RR][M2];
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int j = 0; j < M2; ++j) {
+            const int kx = t + N2 * r + N1 * (2 * j + h), mk = (N - kx) & (N - 1);
+            const cpx<T> ka = Ka[kx], kap = Kap[mk], kb = Kb[kx], kbp = Kbp[mk];
+            const T har = ka.x + kap.x, hai = ka.y - kap.y;
+            const T hbr = kb.x + kbp.x, hbi = kb.y - kbp.y;
+            z[r][j] = make_cpx(har - hbi, hai + hbr);
+        }
+    // step 1: DFT_N2 over k2 for each k1 held, then the twiddle
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        pair_dft_inv<T, M2, N2>(z[r], hi);
+#pragma unroll
+        for (int j = 0; j < M2; ++j) z[r][j] = cmul(z[r][j], w[r][j]);
+    }
+    __syncthreads();  // every group's reads of the spectra are done
+    cpx<T>* E = ex + (u * 4 + 2 * g) * EX;  // this group's exchange region
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int j = 0; j < M2; ++j) E[pair_out<M2>(j, h) * (N1 + 1) + t + N2 * r] = z[r][j];
+    wave_lds_sync();
+    // step 2: DFT_N1 over k1 for m = t -> x[t + N2 n]
+    cpx<T> v[M1];
+#pragma unroll
+    for (int j = 0; j < M1; ++j) v[j] = E[t * (N1 + 1) + 2 * j + h];
+    pair_dft_inv<T, M1, N2>(v, hi);
+    cpx<T>* out = C + (long long)ma * N * N + (long long)yg * N;
+#pragma unroll
+    for (int j = 0; j < M1; ++j) out[t + N2 * pair_out<M1>(j, h)] = v[j];
 }
 
 // ---- P3: inverse FFT along y (four-step), split real/imaginary -----------------
