@@ -394,15 +394,15 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
 }
 
 // ---- P2: rows: forward FFT along x, multiply by conj(D)/n^2, inverse (four-step) -
-// The forward half of one spectral row y for the N2 lanes t of a line, with
-// E its exchange region: on return b[r][k2] holds the row's transform times
-// SCALE conj(D)/n^2 at frequency k1 + N1 k2, k1 = t + N2 r.
-template <typename T, int LOGN, int SCALE_DEN = 1>
-__device__ __forceinline__ void ks_row_forward(const cpx<T>* __restrict__ row, int y, int t,
-                                               cpx<T>* E, const cpx<T>* __restrict__ tw,
-                                               cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2]) {
+// The forward transform of one row for the N2 lanes t of a line, with E its
+// exchange region: on return b[r][k2] holds the row's transform at
+// frequency k1 + N1 k2, k1 = t + N2 r.
+template <typename T, int LOGN>
+__device__ __forceinline__ void ks_row_spectrum(const cpx<T>* __restrict__ row, int t, cpx<T>* E,
+                                                const cpx<T>* __restrict__ tw,
+                                                cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2]) {
     using F = FS<LOGN>;
-    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR;
+    constexpr int N1 = F::N1, N2 = F::N2, RR = F::RR;
     cpx<T> a[N1];
     // forward, step 1: DFT_N1 over n1 of x[N2 n1 + t]
 #pragma unroll
@@ -420,13 +420,20 @@ __device__ __forceinline__ void ks_row_forward(const cpx<T>* __restrict__ row, i
         for (int n2 = 0; n2 < N2; ++n2) b[r][n2] = E[(t + N2 * r) * (N2 + 1) + n2];
         dft_reg<T, N2, false>(b[r]);
     }
-    // multiply by conj(D)/n^2 with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2).
+}
+
+// b (laid out as ks_row_spectrum leaves it, spectral row y) times
+// conj(D)/(SCALE_DEN n^2), with D = [(m1^2 - m2^2) + 2 i nu m1 m2] / (m1^2 + m2^2).
     // Every integer here is exact in T (|m| <= n/2, so m1^2 + m2^2 < 2^24),
     // so the arithmetic runs in T without integer multiplies; 1 / max(den, 1)
     // gives D(0) = 0 because both numerators vanish there.  The imaginary
     // part is 0 on the Nyquist row and column.  The frequency index is
     // t + c with c = N2 r + N1 k2 a multiple of N2 and t < N2, so it lies
     // below n/2 exactly when c does: m1 is t plus a constant.
+template <typename T, int LOGN, int SCALE_DEN>
+__device__ __forceinline__ void ks_multiply(cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2], int y, int t) {
+    using F = FS<LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR;
     const T scale = (T)1 / ((T)N * (T)N * (T)SCALE_DEN);
     const int m2i = signed_freq(y, N);
     const T m2 = (T)m2i, m2sq = m2 * m2;
@@ -446,6 +453,16 @@ __device__ __forceinline__ void ks_row_forward(const cpx<T>* __restrict__ row, i
             b[r][k2] = make_cpx(v.x * dr + v.y * di, v.y * dr - v.x * di);
         }
     }
+}
+
+// The forward half of one spectral row y: transform, then times
+// conj(D)/(SCALE_DEN n^2).
+template <typename T, int LOGN, int SCALE_DEN = 1>
+__device__ __forceinline__ void ks_row_forward(const cpx<T>* __restrict__ row, int y, int t,
+                                               cpx<T>* E, const cpx<T>* __restrict__ tw,
+                                               cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2]) {
+    ks_row_spectrum<T, LOGN>(row, t, E, tw, b);
+    ks_multiply<T, LOGN, SCALE_DEN>(b, y, t);
 }
 
 // The inverse half: from b[r][k2] at frequency k1 + N1 k2 (k1 = t + N2 r),
@@ -596,6 +613,46 @@ __device__ __forceinline__ constexpr int pair_out(int j, int h) {
     return j < M / 2 ? j + h * (M / 2) : j - M / 2 + h * (M / 2) + M;
 }
 
+// ks_multiply for a lane pair (t, t + N2) holding spectral rows y0 (low
+// half) and -y0 (high half), 0 < y0 < n/2, at the same frequencies.  conj(D)
+// of row -y0 is the conjugate of that of row y0, so each half evaluates it,
+// with y0's sign, at half of the frequencies (the low half at k2 < N2/2,
+// the high half at k2 + N2/2) and the halves exchange the values; passing
+// (V, -V) for the imaginary part hands each half its own row's sign.  The
+// result is bit for bit that of ks_multiply (the sign changes are exact).
+template <typename T, int LOGN, int SCALE_DEN>
+__device__ __forceinline__ void ks_multiply_pair(cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2], int y0, int t,
+                                                 bool hi) {
+    using F = FS<LOGN>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, RR = F::RR, HALF = N2 / 2;
+    const T scale = (T)1 / ((T)N * (T)N * (T)SCALE_DEN);
+    const T m2 = (T)y0, m2sq = m2 * m2, two_m2 = (T)2 * m2;
+    // the high half's frequency index is t + c + n/2 with c = N2 r + N1 k2 < n/2,
+    // so its m1 is t - n/2 + c
+    const T tb = (T)t - (hi ? (T)(N / 2) : (T)0);
+    const auto apply = [](cpx<T>& v, T dr, T di) {
+        v = make_cpx(v.x * dr + v.y * di, v.y * dr - v.x * di);
+    };
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+        for (int k2 = 0; k2 < HALF; ++k2) {
+            const int c = N2 * r + N1 * k2;
+            const T m1 = tb + (T)c;
+            const T m1sq = m1 * m1;
+            const T s = scale * recip(fmax(m1sq + m2sq, (T)1));
+            T dr_lo = (m1sq - m2sq) * s, dr_hi = dr_lo;
+            // the Nyquist column n/2 is the high half's c = 0 at t = 0
+            const T v = (c == 0 && hi && t == 0) ? (T)0 : (m1 * two_m2) * s;
+            T di_lo = v, di_hi = -v;
+            half_swap<N2>(dr_lo, dr_hi, hi);
+            half_swap<N2>(di_lo, di_hi, hi);
+            apply(b[r][k2], dr_lo, di_lo);
+            apply(b[r][k2 + HALF], dr_hi, di_hi);
+        }
+    }
+}
+
 template <typename T, int LOGN>
 __global__ void __launch_bounds__((RowPair<T, LOGN>::NT))
 k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw) {
@@ -619,7 +676,11 @@ k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw)
         const cpx<T>* row = C + (long long)((role >> 1) ? mb : ma) * N * N + (long long)y * N;
         cpx<T>* E = ex + line * EX;
         cpx<T> b[RR][N2];
-        ks_row_forward<T, LOGN, 2>(row, y, t, E, tw, b);  // carries the 1/2 of H
+        ks_row_spectrum<T, LOGN>(row, t, E, tw, b);
+        // times conj(D), carrying the 1/2 of H; rows 0 and n/2 are not a
+        // conjugate pair
+        if (q != 0) ks_multiply_pair<T, LOGN, 2>(b, r0, t, (role & 1) != 0);
+        else ks_multiply<T, LOGN, 2>(b, y, t);
         wave_lds_sync();  // the forward exchange's reads are done
 #pragma unroll
         for (int r = 0; r < RR; ++r)
