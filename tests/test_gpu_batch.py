@@ -214,3 +214,27 @@ def test_schedules_round_trip_and_validation(ctx):
             other.plans_load(broken)
     assert other.plans() == before
     other.close()
+
+
+def test_run_path_calls_back_to_back_on_a_stream(ctx):
+    # two calls queued back to back on a non-default stream, with no
+    # synchronisation between them (the second reuses the context's
+    # workspace), give each call's results bit for bit
+    n, J, R = 256, 6, 8
+    side = torch.cuda.Stream()
+    maps = []
+    for k in range(2):
+        _, g1, g2 = S.shear_map(n, 900 + k, 950 + k)
+        maps.append((dev(g1, torch.float32), dev(g2, torch.float32)))
+    def kb():
+        return {"kappa_b": torch.full((n, n), float("nan"), device="cuda")}
+    alone = []
+    for g1, g2 in maps:
+        alone.append(ctx.run_path(g1, g2, J, R, 31, 2.5, out=kb()))
+        torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        outs = [ctx.run_path(g1, g2, J, R, 31, 2.5, out=kb()) for g1, g2 in maps]
+    side.synchronize()
+    for got, ref in zip(outs, alone):
+        for key in ("kappa_e", "kappa_b", "planes", "sigma", "snr", "peaks"):
+            assert torch.equal(got[key], ref[key]), key
