@@ -36,20 +36,23 @@ __global__ void k_zero_i64(long long* p, long long count) {
     if (i < count) p[i] = 0;
 }
 
-// Strict 8-neighbour maxima above thr, periodic.  grid (n*n/1024, nplanes):
-// each thread tests four consecutive pixels of a row (n >= 16, so they share
-// the row) and loads their neighbourhood only if one of them is above thr.
-// One atomic add per wavefront of its count (summed over three ballots of
-// the per-thread counts' bits).
+// Strict 8-neighbour maxima above thr, periodic.  grid (blocks, nplanes) of
+// 1024 threads: each block takes chunks of 4096 pixels of its plane in turn (every thread
+// four consecutive pixels of a row, n >= 16, so they share the row) and
+// loads a neighbourhood only if one of its pixels is above thr.  The block's
+// count gathers in LDS and reaches the plane's counter by one atomic add:
+// device-wide adds to one address serialise, so there are few of them.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_count_peaks(const T* __restrict__ snr, int logn, double thr, long long* __restrict__ counts) {
+    __shared__ unsigned int block_count;
+    if (threadIdx.x == 0) block_count = 0u;
     const int n = 1 << logn, m = n - 1;
     const long long n2 = (long long)n * n;
-    const long long idx = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;  // the first pixel
-    int npk = 0;
-    if (idx < n2) {
-        const T* p = snr + (long long)blockIdx.y * n2;
+    const T* p = snr + (long long)blockIdx.y * n2;
+    unsigned int npk = 0;
+    for (long long idx = ((long long)blockIdx.x * 1024 + threadIdx.x) * 4; idx < n2;
+         idx += (long long)gridDim.x * 4096) {
         const int x = (int)(idx & m), y = (int)(idx >> logn);
         T r[3][6];  // rows y-1, y, y+1 at columns x-1 .. x+4
 #pragma unroll
@@ -60,34 +63,34 @@ k_count_peaks(const T* __restrict__ snr, int logn, double thr, long long* __rest
             cand[i] = (double)r[1][1 + i] > thr;
             any = any || cand[i];
         }
-        if (any) {
+        if (!any) continue;
 #pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const T* row = p + (long long)((y + dy) & m) * n;
-                r[dy + 1][0] = row[(x - 1) & m];
-                r[dy + 1][5] = row[(x + 4) & m];
-                if (dy != 0) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const T* row = p + (long long)((y + dy) & m) * n;
+            r[dy + 1][0] = row[(x - 1) & m];
+            r[dy + 1][5] = row[(x + 4) & m];
+            if (dy != 0) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) r[dy + 1][1 + i] = row[x + i];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const T v = r[1][1 + i];
-                bool pk = cand[i];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-                        if (a != 1 || b != 1) pk = pk & (v > r[a][i + b]);
-                npk += pk ? 1 : 0;
+                for (int i = 0; i < 4; ++i) r[dy + 1][1 + i] = row[x + i];
             }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T v = r[1][1 + i];
+            bool pk = cand[i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    if (a != 1 || b != 1) pk = pk & (v > r[a][i + b]);
+            npk += pk ? 1u : 0u;
+        }
     }
-    const unsigned long long total = (unsigned long long)__popcll(__ballot(npk & 1)) +
-                                     2ull * __popcll(__ballot(npk & 2)) + 4ull * __popcll(__ballot(npk & 4));
-    if ((threadIdx.x & 63) == 0 && total)
-        atomicAdd((unsigned long long*)&counts[blockIdx.y], total);
+    __syncthreads();  // block_count is zeroed
+    if (npk) atomicAdd(&block_count, npk);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count)
+        atomicAdd((unsigned long long*)&counts[blockIdx.y], (unsigned long long)block_count);
 }
 
 // Histogram of peak heights (Sec. 2.2): pixels that are strict 8-neighbour
@@ -215,6 +218,12 @@ k_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* __restrict__ out) {
 }
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
+// Blocks per plane for the peak count: chunks of 4096 pixels, at most 64
+// blocks (so at most 64 atomic adds per plane's counter).
+static unsigned peak_blocks(long long n2) {
+    const long long chunks = (n2 + 4095) / 4096;
+    return (unsigned)(chunks < 64 ? chunks : 64);
+}
 
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
@@ -244,8 +253,7 @@ hipError_t launch_count_peaks(int logn, int nplanes, const T* snr, double thr, l
     hipError_t e = launch_zero_i64(counts, nplanes, s);
     if (e != hipSuccess) return e;
     AMAP_LAUNCH("count_peaks", s,
-                k_count_peaks<T><<<dim3(blocks_for(n2 / 4), nplanes), 256, 0, s>>>(snr, logn, thr,
-                                                                               counts));
+                k_count_peaks<T><<<dim3(peak_blocks(n2), nplanes), 1024, 0, s>>>(snr, logn, thr, counts));
     return hipGetLastError();
 }
 
