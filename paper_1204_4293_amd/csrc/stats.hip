@@ -96,20 +96,21 @@ k_count_peaks(const T* __restrict__ snr, int logn, double thr, long long* __rest
 // Histogram of peak heights (Sec. 2.2): pixels that are strict 8-neighbour
 // maxima of sign*value, periodic, binned by h = sign*value into nbins equal
 // bins over [lo, lo + nbins*width); the bin is floor((h - lo) / width) in
-// double.  Counts gather in LDS and are added to hist once per block.
-// grid (n*n/256, nplanes).
+// double.  grid (blocks, nplanes) of 1024 threads, each block striding over
+// its plane a pixel per thread at a time (at most 64 blocks per plane);
+// counts gather in LDS and are added to hist once per block and bin.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_peak_hist(const T* __restrict__ planes, int logn, int sign, double lo, double width, int nbins,
             long long* __restrict__ hist) {
     extern __shared__ unsigned int bins[];
-    for (int b = threadIdx.x; b < nbins; b += 256) bins[b] = 0u;
+    for (int b = threadIdx.x; b < nbins; b += 1024) bins[b] = 0u;
     __syncthreads();
     const int n = 1 << logn, m = n - 1;
     const long long n2 = (long long)n * n;
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (idx < n2) {
-        const T* p = planes + (long long)blockIdx.y * n2;
+    const T* p = planes + (long long)blockIdx.y * n2;
+    for (long long idx = (long long)blockIdx.x * 1024 + threadIdx.x; idx < n2;
+         idx += (long long)gridDim.x * 1024) {
         const int x = (int)(idx & m), y = (int)(idx >> logn);
         const T h = sign > 0 ? p[idx] : -p[idx];
         // the eight neighbour loads issue together, then one test
@@ -132,7 +133,7 @@ k_peak_hist(const T* __restrict__ planes, int logn, int sign, double lo, double 
     }
     __syncthreads();
     long long* out = hist + (long long)blockIdx.y * nbins;
-    for (int b = threadIdx.x; b < nbins; b += 256)
+    for (int b = threadIdx.x; b < nbins; b += 1024)
         if (bins[b]) atomicAdd((unsigned long long*)&out[b], (unsigned long long)bins[b]);
 }
 
@@ -218,6 +219,11 @@ k_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* __restrict__ out) {
 }
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
+// Blocks per plane for the peak histogram: chunks of 1024 pixels, at most 64.
+static unsigned hist_blocks(long long n2) {
+    const long long chunks = (n2 + 1023) / 1024;
+    return (unsigned)(chunks < 64 ? chunks : 64);
+}
 // Blocks per plane for the peak count: chunks of 4096 pixels, at most 64
 // blocks (so at most 64 atomic adds per plane's counter).
 static unsigned peak_blocks(long long n2) {
@@ -264,7 +270,7 @@ hipError_t launch_peak_hist(int logn, int nplanes, const T* planes, int sign, do
     hipError_t e = launch_zero_i64(hist, (long long)nplanes * nbins, s);
     if (e != hipSuccess) return e;
     AMAP_LAUNCH("peak_hist", s,
-                k_peak_hist<T><<<dim3(blocks_for(n2), nplanes), 256, nbins * sizeof(unsigned int), s>>>(
+                k_peak_hist<T><<<dim3(hist_blocks(n2), nplanes), 1024, nbins * sizeof(unsigned int), s>>>(
                     planes, logn, sign, lo, width, nbins, hist));
     return hipGetLastError();
 }
