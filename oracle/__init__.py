@@ -48,3 +48,7 @@ from .peaks import count_peaks, count_peaks_planes  # noqa: F401
 from .stats import (peak_histogram, peak_histogram_planes, plane_moments,  # noqa: F401
                     plane_moments_stack)
 from .pipeline import run_path  # noqa: F401
+from .bounded import (  # noqa: F401
+    BC_PERIODIC, BC_MIRROR, BC_ZERO, boundary_index, smooth_step_bc, starlet_forward_bc,
+    even_extension, ks_invert_padded,
+)

@@ -1,0 +1,127 @@
+"""Starlet and Kaiser-Squires on fields of any size with stated boundaries (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The paper's fields are periodic squares of side 2^k only where it says so;
+real survey fields have edges and arbitrary sizes, which the paper raises at
+the end of Sec. 5 without fixing a rule.  Readings used here:
+
+  * a field is ny x nx (any sizes >= 2), row-major [y][x];
+  * the starlet cascade is that of ``oracle.starlet`` (B3 taps (1,4,6,4,1)/16
+    at dilation 2^(j-1) for smoothing step j, row pass along x then column
+    pass along y, planes w_1 .. w_{J-1}, c_{J-1}), with every index that
+    falls outside [0, n) taken through one of three boundary rules, applied
+    to c_{j-1} at every step and on each axis separately:
+      - periodic: i mod n;
+      - mirror (whole-sample symmetric): reflection about the first and last
+        samples, c(-i) = c(i) and c(n-1+i) = c(n-1-i), i.e. the index taken
+        modulo 2(n-1) and folded back; the edge samples are not repeated;
+      - zero: c = 0 outside the field;
+  * KS of a bounded field: the shear is zero outside its ny x nx rectangle,
+    which is placed at the origin of a P x P periodic grid (P a power of two,
+    P >= max(ny, nx)); the periodic KS of ``oracle.ks`` is applied there and
+    the ny x nx rectangle is read back.  P = n for an n x n field (n a power
+    of two) is the periodic inversion itself.
+
+Pins (tests/test_oracle_bounded.py): the mirror transform equals the periodic
+transform of the field's even extension (2(ny-1) x 2(nx-1)), restricted to
+the field; the periodic transform of a non-power-of-two, non-square field
+equals Fourier multiplication by the B3 transfer functions; the zero rule
+equals a brute-force two-dimensional sum with zeros outside, on a small
+field; exact reconstruction under every rule; a constant field has zero
+detail planes under the mirror rule; the padded KS with P = n reproduces the
+periodic inversion, and on a small field equals the inversion carried out
+with the O(N^4) brute-force DFT.
+"""
+
+import numpy as np
+
+from .filters import b3_taps
+from .ks import ks_invert
+
+BC_PERIODIC = 0
+BC_MIRROR = 1
+BC_ZERO = 2
+
+
+def boundary_index(i, n, mode):
+    """Index array i mapped into [0, n) by the boundary rule; -1 marks a
+    sample outside the field under the zero rule."""
+    i = np.asarray(i, dtype=np.int64)
+    if mode == BC_PERIODIC:
+        return np.mod(i, n)
+    if mode == BC_MIRROR:
+        if n < 2:
+            raise ValueError("the mirror rule needs n >= 2")
+        p = 2 * (n - 1)
+        k = np.mod(i, p)
+        return np.where(k < n, k, p - k)
+    if mode == BC_ZERO:
+        return np.where((i >= 0) & (i < n), i, -1)
+    raise ValueError("unknown boundary rule %r" % (mode,))
+
+
+def _take(c, idx, axis):
+    """c sampled at boundary-mapped indices idx along axis (0 where idx < 0)."""
+    safe = np.where(idx < 0, 0, idx)
+    out = np.take(c, safe, axis=axis)
+    if np.any(idx < 0):
+        shape = [1, 1]
+        shape[axis] = -1
+        out = np.where(idx.reshape(shape) < 0, 0.0, out)
+    return out
+
+
+def smooth_step_bc(c, s, mode):
+    """One a trous smoothing step at dilation s under a boundary rule."""
+    h = b3_taps()
+    ny, nx = c.shape
+    r = np.zeros_like(c)
+    for t in range(-2, 3):
+        r += h[t + 2] * _take(c, boundary_index(np.arange(nx) + t * s, nx, mode), axis=1)
+    out = np.zeros_like(c)
+    for t in range(-2, 3):
+        out += h[t + 2] * _take(r, boundary_index(np.arange(ny) + t * s, ny, mode), axis=0)
+    return out
+
+
+def starlet_forward_bc(image, J, mode):
+    """Starlet planes [w_1, ..., w_{J-1}, c_{J-1}] of an ny x nx field."""
+    c = np.asarray(image, dtype=np.float64)
+    if c.ndim != 2 or min(c.shape) < 2:
+        raise ValueError("need a 2-D field of at least 2 x 2")
+    if J < 2:
+        raise ValueError("need J >= 2")
+    planes = np.empty((J,) + c.shape, dtype=np.float64)
+    for j in range(1, J):
+        c_next = smooth_step_bc(c, 1 << (j - 1), mode)
+        planes[j - 1] = c - c_next
+        c = c_next
+    planes[J - 1] = c
+    return planes
+
+
+def even_extension(a):
+    """Whole-sample symmetric extension of an ny x nx field to 2(ny-1) x 2(nx-1)."""
+    a = np.asarray(a, dtype=np.float64)
+    ny, nx = a.shape
+    iy = boundary_index(np.arange(2 * (ny - 1)), ny, BC_MIRROR)
+    ix = boundary_index(np.arange(2 * (nx - 1)), nx, BC_MIRROR)
+    return a[np.ix_(iy, ix)]
+
+
+def ks_invert_padded(g1, g2, P):
+    """KS of an ny x nx shear field zero-extended into a P x P periodic grid;
+    returns (kappa_E, kappa_B) on the field's rectangle."""
+    g1 = np.asarray(g1, dtype=np.float64)
+    g2 = np.asarray(g2, dtype=np.float64)
+    ny, nx = g1.shape
+    assert g2.shape == (ny, nx)
+    if P < max(ny, nx) or P & (P - 1):
+        raise ValueError("P must be a power of two >= max(ny, nx)")
+    a1 = np.zeros((P, P))
+    a2 = np.zeros((P, P))
+    a1[:ny, :nx] = g1
+    a2[:ny, :nx] = g2
+    kE, kB = ks_invert(a1, a2)
+    return kE[:ny, :nx].copy(), kB[:ny, :nx].copy()
