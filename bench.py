@@ -18,6 +18,9 @@ Printed as one JSON line.  Extra objects:
   statistics   plane moments and peak-height histograms on the step's planes
   direct_vs_starlet  map_direct at theta = 2..64 (cut theta) vs KS + starlet
                with J = log2 theta + 1 on the 1024^2 map (the paper's comparison)
+  bounded      a 1000 x 1000 field with edges (a crop of the map): KS of the
+               field zero-extended into a 2048^2 grid + starlet J = 7 under the
+               mirror edge rule
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -486,6 +489,29 @@ def main():
         stats[name] = {"us_per_call": us, "alg_bytes": nbytes, "alg_GBps": nbytes / us / 1e3,
                        "hbm_alg_frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
 
+    # a field with edges and a side that is not a power of two: the map's
+    # 1000 x 1000 corner, KS zero-extended into 2048^2, starlet J = 7 under
+    # the mirror rule
+    NB, PB = 1000, 2048
+    b1, b2 = t1[:NB, :NB].contiguous(), t2[:NB, :NB].contiguous()
+    bk = torch.empty((NB, NB), dtype=torch.float32, device=dev)
+    bpl = torch.empty((J, NB, NB), dtype=torch.float32, device=dev)
+
+    def bounded_once():
+        ctx.ks_invert_padded(b1, b2, PB, kappa_e=bk)
+        ctx.starlet_forward_bc(bk, J, amap.BC_MIRROR, planes=bpl)
+    bounded_once()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(20):
+        bounded_once()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_b = ev0.elapsed_time(ev1) / 20
+    bounded = {"workload": "1000x1000 float32 field (corner of the step's map), KS zero-extended "
+                           "into 2048x2048, starlet J=7, mirror edges",
+               "ms_per_map": t_b, "value": NB * NB * J / (t_b * 1e3), "unit": "Mpix·scales/s"}
+
     batched = served = None
     if not args.no_batched:
         print("bench: uneven batch", file=sys.stderr, flush=True)
@@ -510,6 +536,7 @@ def main():
                                / (HBM_PEAK_GBS * 1e9),
         "plain": plain, "batched": batched, "served": served, "statistics": stats,
         "direct_vs_starlet": direct,
+        "bounded": bounded,
         "roofline": roofline,
         "kernels": kernels,
         # tile schedules the autotuner chose for this run: [j0, scales, tile

@@ -65,6 +65,17 @@ typedef enum {
     AMAP_FILTER_JBJ04 = 2
 } amap_filter;
 
+/* Edge rules for fields that are not periodic squares (the paper raises
+ * survey-field edges at the end of Sec. 5 and fixes no rule): an index
+ * outside [0, n) is taken modulo n (periodic), reflected about the first and
+ * last samples with period 2(n-1), the edge samples not repeated (mirror),
+ * or the sample is 0 (zero). */
+typedef enum {
+    AMAP_BC_PERIODIC = 0,
+    AMAP_BC_MIRROR = 1,
+    AMAP_BC_ZERO = 2
+} amap_boundary;
+
 typedef struct amap_ctx*  amap_ctx_t;
 typedef struct amap_plan* amap_plan_t;
 typedef struct amap_server* amap_server_t;
@@ -161,6 +172,34 @@ amap_status amap_ks_invert(amap_ctx_t ctx, amap_dtype dt, int n,
  */
 amap_status amap_starlet_forward(amap_ctx_t ctx, amap_dtype dt, int n, int J,
                                  const void* kappa, void* planes, void* stream);
+
+/*
+ * Starlet decomposition of an ny x nx field of any sides in [2, 16384]
+ * (Sec. 3 cascade with the B3 taps of Sec. 4.2, as amap_starlet_forward)
+ * under an edge rule `boundary` (amap_boundary), applied to c_{j-1} on each
+ * axis at every smoothing step; 2 <= J <= 16.  image: ny*nx row-major;
+ * planes: J*ny*nx, w_1 .. w_{J-1}, c_{J-1}; they may not overlap.  The
+ * decomposition is exact under every rule (sum of the planes = image); the
+ * detail planes have zero mean only under the periodic rule.  Uses ny*nx
+ * elements of the context's workspace.
+ */
+amap_status amap_starlet_forward_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int J,
+                                    int boundary, const void* image, void* planes,
+                                    void* stream);
+
+/*
+ * Kaiser-Squires inversion (as amap_ks_invert) of an ny x nx shear field that
+ * is zero outside its rectangle: the field is placed at the origin of a
+ * P x P periodic grid (P a power of two in [16, 4096], P >= ny, nx), inverted
+ * there, and the ny x nx rectangle of kappa_E (and of kappa_B, if not NULL)
+ * is written to kappa_e / kappa_b (ny*nx each, row-major).  P = n for an
+ * n x n field is amap_ks_invert itself; P = 2 max(ny, nx) keeps the periodic
+ * images of the field from overlapping it.  Outputs may not alias inputs.
+ * Uses 6 P^2 elements of the context's workspace.
+ */
+amap_status amap_ks_invert_padded(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int P,
+                                  const void* g1, const void* g2, void* kappa_e,
+                                  void* kappa_b, void* stream);
 
 /* Exact inverse of the decomposition (Sec. 3): kappa_out = c_{J-1} + sum w_j.
  * planes: J*n*n; kappa_out: n*n (may not overlap planes). */

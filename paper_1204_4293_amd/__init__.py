@@ -21,6 +21,7 @@ HEADER = os.path.join(ROOT, "include", "amap.h")
 
 F32, F64 = 0, 1
 FILTER_STARLET, FILTER_S98, FILTER_JBJ04 = 0, 1, 2
+BC_PERIODIC, BC_MIRROR, BC_ZERO = 0, 1, 2
 _STATUS = {0: "AMAP_OK", 1: "AMAP_E_INVAL", 2: "AMAP_E_NOMEM", 3: "AMAP_E_HIP",
            4: "AMAP_E_UNSUPPORTED", 5: "AMAP_E_BUSY"}
 E_NOMEM, E_BUSY = 2, 5
@@ -76,6 +77,8 @@ def load():
         "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
         "amap_starlet_forward": (I, [P, I, I, I, P, P, P]),
+        "amap_starlet_forward_bc": (I, [P, I, I, I, I, I, P, P, P]),
+        "amap_ks_invert_padded": (I, [P, I, I, I, I, P, P, P, P, P]),
         "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
         "amap_map_direct": (I, [P, I, I, P, P, D, I, D, D, P, P]),
         "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
@@ -227,6 +230,24 @@ class Context:
         _check(load().amap_starlet_forward(self._h, _dt(kappa), n, int(J), _ptr(kappa),
                                            _ptr(planes), _stream()))
         return planes
+
+    def starlet_forward_bc(self, image, J, boundary=BC_MIRROR, planes=None):
+        """Starlet planes of an ny x nx field under an edge rule (BC_*)."""
+        ny, nx = int(image.shape[-2]), int(image.shape[-1])
+        planes = self._empty((J, ny, nx), image) if planes is None else planes
+        _check(load().amap_starlet_forward_bc(self._h, _dt(image), ny, nx, int(J), int(boundary),
+                                              _ptr(image), _ptr(planes), _stream()))
+        return planes
+
+    def ks_invert_padded(self, g1, g2, P, kappa_e=None, kappa_b=None, want_b=False):
+        """KS of an ny x nx field zero-extended into a P x P grid."""
+        ny, nx = int(g1.shape[-2]), int(g1.shape[-1])
+        kappa_e = self._empty((ny, nx), g1) if kappa_e is None else kappa_e
+        if kappa_b is None and want_b:
+            kappa_b = self._empty((ny, nx), g1)
+        _check(load().amap_ks_invert_padded(self._h, _dt(g1), ny, nx, int(P), _ptr(g1), _ptr(g2),
+                                            _ptr(kappa_e), _ptr(kappa_b), _stream()))
+        return kappa_e, kappa_b
 
     def starlet_reconstruct(self, planes, out=None):
         J, n = planes.shape[0], _side(planes)

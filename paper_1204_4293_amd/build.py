@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libamap.so")
 
-SOURCES = ["api.hip", "ks_fft.hip", "starlet.hip", "stats.hip", "direct.hip"]
+SOURCES = ["api.hip", "ks_fft.hip", "starlet.hip", "stats.hip", "direct.hip", "bounded.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -150,4 +150,19 @@ template <typename T>
 hipError_t launch_map_direct(int logn, const T* g1, const T* g2, int R, const int* half,
                              const T* wc, const T* ws, T* out, hipStream_t s);
 
+// Starlet of an ny x nx field (any sizes >= 2) under a boundary rule
+// (0 periodic, 1 mirror: whole-sample symmetric, 2 zero outside): J planes
+// w_1 .. w_{J-1}, c_{J-1}, each ny*nx, in `planes`; `tmp` holds ny*nx.
+template <typename T>
+hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T* planes, T* tmp,
+                             hipStream_t s);
+
+// Zero extension of an ny x nx pair of fields into P x P arrays, and the
+// ny x nx rectangle of P x P arrays read back (kB_p/kB may be null).
+template <typename T>
+hipError_t launch_pad2(const T* g1, const T* g2, int ny, int nx, int P, T* p1, T* p2, hipStream_t s);
+template <typename T>
+hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB,
+                        hipStream_t s);
+
 }  // namespace amap

@@ -678,6 +678,82 @@ amap_status amap_starlet_forward(amap_ctx_t c, amap_dtype dt, int n, int J, cons
                                    (long long)J * n2, (double*)c->ws.ptr, s);
 }
 
+amap_status amap_starlet_forward_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int J,
+                                    int boundary, const void* image, void* planes, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    if (ny < 2 || nx < 2 || ny > 16384 || nx > 16384)
+        return fail(AMAP_E_INVAL, "field sides must be in [2, 16384] (got %d x %d)", ny, nx);
+    if (J < 2 || J > 16) return fail(AMAP_E_INVAL, "J must be in [2, 16] (got %d)", J);
+    if (boundary < AMAP_BC_PERIODIC || boundary > AMAP_BC_ZERO)
+        return fail(AMAP_E_INVAL, "boundary must be AMAP_BC_PERIODIC, _MIRROR or _ZERO (got %d)", boundary);
+    AMAP_TRY(check_ptr(image, "image"));
+    AMAP_TRY(check_ptr(planes, "planes"));
+    const size_t plane = (size_t)ny * nx * esize(dt);
+    if (overlaps(image, plane, planes, plane * J))
+        return fail(AMAP_E_INVAL, "planes may not overlap image");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    AMAP_TRY(c->ws.reserve(plane));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt == AMAP_F32)
+        AMAP_HIP(launch_starlet_bc<float>(ny, nx, J, boundary, (const float*)image, (float*)planes,
+                                          (float*)c->ws.ptr, s), "bounded starlet kernels");
+    else
+        AMAP_HIP(launch_starlet_bc<double>(ny, nx, J, boundary, (const double*)image, (double*)planes,
+                                           (double*)c->ws.ptr, s), "bounded starlet kernels");
+    return AMAP_OK;
+}
+
+amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, int P,
+                                  const void* g1, const void* g2, void* kappa_e, void* kappa_b,
+                                  void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(P));
+    if (ny < 1 || nx < 1 || ny > P || nx > P)
+        return fail(AMAP_E_INVAL, "field %d x %d must fit the %d x %d grid", ny, nx, P, P);
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(kappa_e, "kappa_e"));
+    AMAP_TRY(check_ptr(kappa_b, "kappa_b", false));
+    const size_t bytes = (size_t)ny * nx * esize(dt);
+    if (overlaps(kappa_e, bytes, g1, bytes) || overlaps(kappa_e, bytes, g2, bytes) ||
+        overlaps(kappa_b, bytes, g1, bytes) || overlaps(kappa_b, bytes, g2, bytes) ||
+        overlaps(kappa_e, bytes, kappa_b, bytes))
+        return fail(AMAP_E_INVAL, "outputs may not overlap inputs or each other");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    // workspace: complex spectrum (2 planes), padded g1, g2, kappa_E, kappa_B
+    const size_t pb = align256((size_t)P * P * esize(dt));
+    AMAP_TRY(c->ws.reserve(6 * pb));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(c->ws.ptr);
+    const int logn = ilog2(P);
+    if (dt == AMAP_F32) {
+        float *p1 = (float*)(w + 2 * pb), *p2 = (float*)(w + 3 * pb);
+        float *e = (float*)(w + 4 * pb), *b = kappa_b ? (float*)(w + 5 * pb) : nullptr;
+        AMAP_HIP(launch_pad2<float>((const float*)g1, (const float*)g2, ny, nx, P, p1, p2, s), "pad kernel");
+        AMAP_TRY(enqueue_ks<float>(c, logn, 1, p1, p2, 0, (cpx<float>*)w, e, b, (long long)P * P,
+                                   false, 0, 0, s));
+        AMAP_HIP(launch_crop2<float>(e, b, P, ny, nx, (float*)kappa_e, (float*)kappa_b, s), "crop kernel");
+    } else {
+        double *p1 = (double*)(w + 2 * pb), *p2 = (double*)(w + 3 * pb);
+        double *e = (double*)(w + 4 * pb), *b = kappa_b ? (double*)(w + 5 * pb) : nullptr;
+        AMAP_HIP(launch_pad2<double>((const double*)g1, (const double*)g2, ny, nx, P, p1, p2, s),
+                 "pad kernel");
+        AMAP_TRY(enqueue_ks<double>(c, logn, 1, p1, p2, 0, (cpx<double>*)w, e, b, (long long)P * P,
+                                    false, 0, 0, s));
+        AMAP_HIP(launch_crop2<double>(e, b, P, ny, nx, (double*)kappa_e, (double*)kappa_b, s),
+                 "crop kernel");
+    }
+    return AMAP_OK;
+}
+
 amap_status amap_starlet_reconstruct(amap_ctx_t c, amap_dtype dt, int n, int J,
                                      const void* planes, void* kappa_out, void* stream) {
     g_last_error.clear();

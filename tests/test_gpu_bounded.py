@@ -1,0 +1,118 @@
+"""Bounded fields through the C ABI against the FP64 oracle: the starlet of
+any-size fields under periodic, mirror and zero edge rules, and KS of a field
+zero-extended into a power-of-two grid.
+
+FP32 within 1e-5 * rms(input) and FP64 within 1e-10 * rms(input) of the
+oracle, on the same inputs; the padded KS with P = n is the periodic
+inversion bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth as S
+import paper_1204_4293_amd as amap
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-5, torch.float64: 1e-10}
+RULES = [amap.BC_PERIODIC, amap.BC_MIRROR, amap.BC_ZERO]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = amap.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rms(a):
+    return float(np.sqrt(np.mean(np.asarray(a, dtype=np.float64) ** 2)))
+
+
+def field(ny, nx, seed):
+    """A GRF convergence map cropped to ny x nx (a field with edges)."""
+    n = 16
+    while n < max(ny, nx):
+        n *= 2
+    return S.grf_kappa(n, seed)[:ny, :nx]
+
+
+@pytest.mark.parametrize("ny,nx,J", [(16, 16, 3), (37, 53, 5), (100, 257, 6), (2, 2, 3),
+                                     (3, 700, 7), (1000, 1000, 7)])
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_bounded_starlet_matches_oracle(ctx, ny, nx, J, rule, dtype):
+    if dtype == torch.float64 and ny * nx > 300000:
+        pytest.skip("FP64 checked on the smaller fields")
+    print("bounded starlet %dx%d J=%d rule=%d %s" % (ny, nx, J, rule, dtype), flush=True)
+    a = field(ny, nx, 40 + ny + nx)
+    got = ctx.starlet_forward_bc(dev(a, dtype), J, rule)
+    torch.cuda.synchronize()
+    ref = O.starlet_forward_bc(a, J, rule)
+    err = float(np.max(np.abs(got.double().cpu().numpy() - ref)))
+    assert err <= TOL[dtype] * rms(a), err
+    # exact decomposition under every rule
+    rec = got.double().sum(0).cpu().numpy()
+    assert float(np.max(np.abs(rec - a))) <= TOL[dtype] * rms(a)
+
+
+def test_bounded_periodic_square_agrees_with_the_tiled_transform(ctx):
+    kappa = S.grf_kappa(256, 9)
+    t = dev(kappa, torch.float32)
+    a = ctx.starlet_forward_bc(t, 6, amap.BC_PERIODIC)
+    b = ctx.starlet_forward(t, 6)
+    torch.cuda.synchronize()
+    assert float((a.double() - b.double()).abs().max()) <= 1e-5 * rms(kappa)
+
+
+@pytest.mark.parametrize("ny,nx,P", [(37, 53, 64), (100, 200, 256), (16, 16, 16), (1000, 1000, 2048),
+                                     (1, 300, 512)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_padded_ks_matches_oracle(ctx, ny, nx, P, dtype):
+    if dtype == torch.float64 and P > 512:
+        pytest.skip("FP64 checked on the smaller grids")
+    print("padded KS %dx%d P=%d %s" % (ny, nx, P, dtype), flush=True)
+    n = 16
+    while n < max(ny, nx):
+        n *= 2
+    _, g1, g2 = S.shear_map(n, 70 + ny, 71 + nx)
+    g1, g2 = g1[:ny, :nx], g2[:ny, :nx]
+    kE, kB = ctx.ks_invert_padded(dev(g1, dtype), dev(g2, dtype), P, want_b=True)
+    torch.cuda.synchronize()
+    rE, rB = O.ks_invert_padded(g1, g2, P)
+    scale = max(rms(rE), rms(rB))
+    assert float(np.max(np.abs(kE.double().cpu().numpy() - rE))) <= TOL[dtype] * scale
+    assert float(np.max(np.abs(kB.double().cpu().numpy() - rB))) <= TOL[dtype] * scale
+    kE_only, none = ctx.ks_invert_padded(dev(g1, dtype), dev(g2, dtype), P)
+    torch.cuda.synchronize()
+    assert none is None and torch.equal(kE_only, kE)
+
+
+def test_padded_ks_with_p_equal_n_is_the_periodic_inversion(ctx):
+    _, g1, g2 = S.shear_map(128, 5, 6)
+    t1, t2 = dev(g1, torch.float32), dev(g2, torch.float32)
+    a = ctx.ks_invert_padded(t1, t2, 128, want_b=True)
+    b = ctx.ks_invert(t1, t2, want_b=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_bounded_calls_reject_bad_arguments(ctx):
+    t = torch.zeros((20, 30), device="cuda")
+    with pytest.raises(amap.AmapError):
+        ctx.starlet_forward_bc(t, 1, amap.BC_MIRROR)
+    with pytest.raises(amap.AmapError):
+        ctx.starlet_forward_bc(t, 3, 3)
+    with pytest.raises(amap.AmapError):
+        ctx.starlet_forward_bc(torch.zeros((1, 30), device="cuda"), 3, amap.BC_MIRROR)
+    with pytest.raises(amap.AmapError):
+        ctx.ks_invert_padded(t, t, 24)          # not a power of two
+    with pytest.raises(amap.AmapError):
+        ctx.ks_invert_padded(t, t, 16)          # smaller than the field
