@@ -17,6 +17,12 @@ the end of Sec. 5 without fixing a rule.  Readings used here:
         samples, c(-i) = c(i) and c(n-1+i) = c(n-1-i), i.e. the index taken
         modulo 2(n-1) and folded back; the edge samples are not repeated;
       - zero: c = 0 outside the field;
+  * noise maps of a bounded field follow Sec. 1 and Sec. 5.1 as in
+    ``oracle.noise``: realisation r rotates every pixel's shear by
+    2 pi u, u the Philox uniform of flat pixel index y * nx + x (the
+    definition of ``oracle.rng``), and the rotated field goes through the
+    same padded KS and bounded starlet as the signal; sigma_j is the
+    unbiased per-pixel sample standard deviation (Welford's update);
   * KS of a bounded field: the shear is zero outside its ny x nx rectangle,
     which is placed at the origin of a P x P periodic grid (P a power of two,
     P >= max(ny, nx)); the periodic KS of ``oracle.ks`` is applied there and
@@ -31,13 +37,19 @@ equals a brute-force two-dimensional sum with zeros outside, on a small
 field; exact reconstruction under every rule; a constant field has zero
 detail planes under the mirror rule; the padded KS with P = n reproduces the
 periodic inversion, and on a small field equals the inversion carried out
-with the O(N^4) brute-force DFT.
+with the O(N^4) brute-force DFT; the bounded noise sigma under the periodic
+rule with P = n equals ``oracle.noise.noise_sigma``, and its variance tracks
+the closed form 1/2 sum_y |gamma(y)|^2 (A1(x, y)^2 + A2(x, y)^2), A1 and A2
+the responses of w_j(x) to unit gamma1 and gamma2 at y, within chi-square
+scatter.
 """
 
 import numpy as np
 
 from .filters import b3_taps
 from .ks import ks_invert
+from .noise import rotate_shear
+from .rng import phase_uniforms_u32
 
 BC_PERIODIC = 0
 BC_MIRROR = 1
@@ -125,3 +137,24 @@ def ks_invert_padded(g1, g2, P):
     a2[:ny, :nx] = g2
     kE, kB = ks_invert(a1, a2)
     return kE[:ny, :nx].copy(), kB[:ny, :nx].copy()
+
+
+def noise_sigma_bc(g1, g2, P, J, mode, n_real, seed):
+    """Per-pixel, per-scale noise sigma_j of an ny x nx field (shape (J-1, ny, nx))."""
+    if n_real < 2:
+        raise ValueError("need at least two realisations")
+    g1 = np.asarray(g1, dtype=np.float64)
+    g2 = np.asarray(g2, dtype=np.float64)
+    ny, nx = g1.shape
+    mean = np.zeros((J - 1, ny, nx))
+    m2 = np.zeros((J - 1, ny, nx))
+    for r in range(n_real):
+        v = phase_uniforms_u32(ny * nx, seed, r)
+        u = ((v >> np.uint32(8)).astype(np.float64) * 2.0 ** -24).reshape(ny, nx)
+        a1, a2 = rotate_shear(g1, g2, u)
+        kE, _ = ks_invert_padded(a1, a2, P)
+        w = starlet_forward_bc(kE, J, mode)[:J - 1]
+        delta = w - mean
+        mean += delta / (r + 1)
+        m2 += delta * (w - mean)
+    return np.sqrt(m2 / (n_real - 1))

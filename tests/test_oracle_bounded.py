@@ -157,3 +157,33 @@ def test_bad_arguments():
         O.ks_invert_padded(np.zeros((5, 6)), np.zeros((5, 6)), 4)
     with pytest.raises(ValueError):
         O.ks_invert_padded(np.zeros((5, 6)), np.zeros((5, 6)), 12)
+
+
+def test_bounded_noise_reduces_to_the_periodic_noise():
+    _, g1, g2 = S.shear_map(32, 11, 12)
+    a = O.noise_sigma_bc(g1, g2, 32, 4, O.BC_PERIODIC, 5, 77)
+    b = O.noise_sigma(g1, g2, 4, 5, 77)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("mode", [O.BC_MIRROR, O.BC_ZERO])
+def test_bounded_noise_variance_tracks_its_expectation(mode):
+    # var w_j(x) = 1/2 sum_y |gamma(y)|^2 (A1(x,y)^2 + A2(x,y)^2) for uniform
+    # rotation angles; A1, A2 probed with unit shears at every pixel
+    ny, nx, P, J, R = 10, 12, 32, 3, 1200
+    rng = np.random.default_rng(20 + mode)
+    g1, g2 = 0.3 * rng.standard_normal((ny, nx)), 0.3 * rng.standard_normal((ny, nx))
+    expect = np.zeros((J - 1, ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            d = np.zeros((ny, nx))
+            d[y, x] = 1.0
+            A1 = O.starlet_forward_bc(O.ks_invert_padded(d, 0 * d, P)[0], J, mode)[:J - 1]
+            A2 = O.starlet_forward_bc(O.ks_invert_padded(0 * d, d, P)[0], J, mode)[:J - 1]
+            expect += 0.5 * (g1[y, x] ** 2 + g2[y, x] ** 2) * (A1 ** 2 + A2 ** 2)
+    got = O.noise_sigma_bc(g1, g2, P, J, mode, R, 5) ** 2
+    ratio = got / expect
+    # chi-square scatter of a sample variance over R draws: sqrt(2/(R-1)) ~ 4%;
+    # the pixel mean of the ratio is far tighter
+    assert abs(float(ratio.mean()) - 1.0) < 0.02
+    assert float(np.max(np.abs(ratio - 1.0))) < 6 * np.sqrt(2.0 / (R - 1)) * 1.5
