@@ -201,6 +201,24 @@ amap_status amap_ks_invert_padded(amap_ctx_t ctx, amap_dtype dt, int ny, int nx,
                                   const void* g1, const void* g2, void* kappa_e,
                                   void* kappa_b, void* stream);
 
+/*
+ * Noise maps of an ny x nx field with edges (Sec. 1; Sec. 5.1, as
+ * amap_noise_maps): realisation r = 0 .. n_real-1 rotates every pixel's
+ * shear by 2 pi u, u the Philox4x64-10 uniform of flat pixel index
+ * y*nx + x (amap_phase_uniforms with n*n replaced by ny*nx); the rotated
+ * field goes through amap_ks_invert_padded (grid P) and
+ * amap_starlet_forward_bc (rule `boundary`).  sigma_j is the per-pixel
+ * unbiased sample standard deviation (running mean and squared deviations
+ * in double, Welford's update).  If snr is not NULL, planes_signal (J*ny*nx,
+ * the signal's planes from the same two calls) must be given and
+ * snr_j = w_j / sigma_j (0 where sigma_j = 0).  sigma, snr: (J-1)*ny*nx.
+ * Sides >= 2 and <= P; n_real >= 2.  One launch sequence per realisation.
+ */
+amap_status amap_noise_maps_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int P, int J,
+                               int boundary, const void* g1, const void* g2, int n_real,
+                               uint64_t seed, const void* planes_signal, void* sigma, void* snr,
+                               void* stream);
+
 /* Exact inverse of the decomposition (Sec. 3): kappa_out = c_{J-1} + sum w_j.
  * planes: J*n*n; kappa_out: n*n (may not overlap planes). */
 amap_status amap_starlet_reconstruct(amap_ctx_t ctx, amap_dtype dt, int n, int J,

@@ -79,6 +79,7 @@ def load():
         "amap_starlet_forward": (I, [P, I, I, I, P, P, P]),
         "amap_starlet_forward_bc": (I, [P, I, I, I, I, I, P, P, P]),
         "amap_ks_invert_padded": (I, [P, I, I, I, I, P, P, P, P, P]),
+        "amap_noise_maps_bc": (I, [P, I, I, I, I, I, I, P, P, I, U64, P, P, P, P]),
         "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
         "amap_map_direct": (I, [P, I, I, P, P, D, I, D, D, P, P]),
         "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
@@ -248,6 +249,17 @@ class Context:
         _check(load().amap_ks_invert_padded(self._h, _dt(g1), ny, nx, int(P), _ptr(g1), _ptr(g2),
                                             _ptr(kappa_e), _ptr(kappa_b), _stream()))
         return kappa_e, kappa_b
+
+    def noise_maps_bc(self, g1, g2, P, J, boundary, n_real, seed, planes_signal=None,
+                      want_snr=True):
+        """sigma (and S/N) of an ny x nx field with edges; returns (sigma, snr)."""
+        ny, nx = int(g1.shape[-2]), int(g1.shape[-1])
+        sigma = self._empty((J - 1, ny, nx), g1)
+        snr = self._empty((J - 1, ny, nx), g1) if (want_snr and planes_signal is not None) else None
+        _check(load().amap_noise_maps_bc(self._h, _dt(g1), ny, nx, int(P), int(J), int(boundary),
+                                         _ptr(g1), _ptr(g2), int(n_real), int(seed),
+                                         _ptr(planes_signal), _ptr(sigma), _ptr(snr), _stream()))
+        return sigma, snr
 
     def starlet_reconstruct(self, planes, out=None):
         J, n = planes.shape[0], _side(planes)

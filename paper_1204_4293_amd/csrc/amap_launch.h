@@ -165,4 +165,22 @@ template <typename T>
 hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB,
                         hipStream_t s);
 
+// Noise realisations of a bounded field: the ny x nx shears rotated by the
+// Philox phases of realisation r (flat pixel index y*nx + x) and written
+// into the field's rectangle of the P x P arrays p1, p2 (their rest is left
+// as it is: cleared once by launch_zero2); Welford's update of the running
+// mean M and squared deviations M2 (double, `count` elements) with the r-th
+// value w (r = 0 writes them unread); sigma = sqrt(M2/(R-1)) and, if snr is
+// not null, snr = w_signal / sigma (0 where sigma = 0).
+template <typename T>
+hipError_t launch_rotate_scatter(const T* g1, const T* g2, int ny, int nx, int P, uint64_t seed,
+                                 uint64_t r, T* p1, T* p2, hipStream_t s);
+template <typename T>
+hipError_t launch_zero2(T* p1, T* p2, long long count, hipStream_t s);
+template <typename T>
+hipError_t launch_welford_bc(const T* w, double* M, double* M2, long long count, int r, hipStream_t s);
+template <typename T>
+hipError_t launch_sigma_snr_bc(const double* M2, int R, const T* w_signal, T* sigma, T* snr,
+                               long long count, hipStream_t s);
+
 }  // namespace amap

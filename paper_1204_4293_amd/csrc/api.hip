@@ -754,6 +754,83 @@ amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, i
     return AMAP_OK;
 }
 
+}  // extern "C"
+
+template <typename T>
+static amap_status enqueue_noise_bc(const amap_ctx* c, char* w, int ny, int nx, int P, int J,
+                                    int boundary, const T* g1, const T* g2, int n_real, uint64_t seed,
+                                    const T* planes_signal, T* sigma, T* snr, hipStream_t s) {
+    const size_t esz = sizeof(T);
+    const size_t pb = align256((size_t)P * P * esz), fb = align256((size_t)ny * nx * esz);
+    const long long cnt = (long long)(J - 1) * ny * nx;
+    char* q = w;
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(q);  q += 2 * pb;
+    T* p1 = reinterpret_cast<T*>(q);           q += pb;
+    T* p2 = reinterpret_cast<T*>(q);           q += pb;
+    T* ke = reinterpret_cast<T*>(q);           q += pb;
+    T* kap = reinterpret_cast<T*>(q);          q += fb;
+    T* tmp = reinterpret_cast<T*>(q);          q += fb;
+    T* pl = reinterpret_cast<T*>(q);           q += align256((size_t)J * ny * nx * esz);
+    double* M = reinterpret_cast<double*>(q);  q += align256((size_t)cnt * 8);
+    double* M2 = reinterpret_cast<double*>(q);
+    // the grid outside the field stays zero: the KS never writes its inputs
+    AMAP_HIP(launch_zero2<T>(p1, p2, (long long)P * P, s), "zero kernel");
+    for (int r = 0; r < n_real; ++r) {
+        AMAP_HIP(launch_rotate_scatter<T>(g1, g2, ny, nx, P, seed, (uint64_t)r, p1, p2, s),
+                 "rotation kernel");
+        AMAP_TRY(enqueue_ks<T>(c, ilog2(P), 1, p1, p2, 0, C, ke, nullptr, (long long)P * P, false, 0,
+                               0, s));
+        AMAP_HIP(launch_crop2<T>(ke, nullptr, P, ny, nx, kap, nullptr, s), "crop kernel");
+        AMAP_HIP(launch_starlet_bc<T>(ny, nx, J, boundary, kap, pl, tmp, s), "bounded starlet kernels");
+        AMAP_HIP(launch_welford_bc<T>(pl, M, M2, cnt, r, s), "statistics kernel");
+    }
+    AMAP_HIP(launch_sigma_snr_bc<T>(M2, n_real, planes_signal, sigma, snr, cnt, s), "sigma kernel");
+    return AMAP_OK;
+}
+
+extern "C" {
+
+amap_status amap_noise_maps_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int P, int J,
+                               int boundary, const void* g1, const void* g2, int n_real,
+                               uint64_t seed, const void* planes_signal, void* sigma, void* snr,
+                               void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(P));
+    if (ny < 2 || nx < 2 || ny > P || nx > P)
+        return fail(AMAP_E_INVAL, "field %d x %d must have sides >= 2 and fit the %d x %d grid", ny, nx,
+                    P, P);
+    if (J < 2 || J > 16) return fail(AMAP_E_INVAL, "J must be in [2, 16] (got %d)", J);
+    if (boundary < AMAP_BC_PERIODIC || boundary > AMAP_BC_ZERO)
+        return fail(AMAP_E_INVAL, "boundary must be AMAP_BC_PERIODIC, _MIRROR or _ZERO (got %d)", boundary);
+    if (n_real < 2) return fail(AMAP_E_INVAL, "n_real must be >= 2 (got %d)", n_real);
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(sigma, "sigma"));
+    AMAP_TRY(check_ptr(snr, "snr", false));
+    if (snr) AMAP_TRY(check_ptr(planes_signal, "planes_signal (needed for snr)"));
+    const size_t f = (size_t)ny * nx * esize(dt), fd = f * (J - 1);
+    if (overlaps(sigma, fd, g1, f) || overlaps(sigma, fd, g2, f) || overlaps(snr, fd, g1, f) ||
+        overlaps(snr, fd, g2, f) || overlaps(sigma, fd, snr, fd) ||
+        overlaps(sigma, fd, planes_signal, f * J) || overlaps(snr, fd, planes_signal, f * J))
+        return fail(AMAP_E_INVAL, "outputs may not overlap inputs or each other");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    const size_t pb = align256((size_t)P * P * esize(dt)), fb = align256(f);
+    AMAP_TRY(c->ws.reserve(5 * pb + 2 * fb + align256(f * J) + 2 * align256((size_t)(J - 1) * ny * nx * 8)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(c->ws.ptr);
+    if (dt == AMAP_F32)
+        return enqueue_noise_bc<float>(c, w, ny, nx, P, J, boundary, (const float*)g1, (const float*)g2,
+                                       n_real, seed, (const float*)planes_signal, (float*)sigma,
+                                       (float*)snr, s);
+    return enqueue_noise_bc<double>(c, w, ny, nx, P, J, boundary, (const double*)g1, (const double*)g2,
+                                    n_real, seed, (const double*)planes_signal, (double*)sigma,
+                                    (double*)snr, s);
+}
+
 amap_status amap_starlet_reconstruct(amap_ctx_t c, amap_dtype dt, int n, int J,
                                      const void* planes, void* kappa_out, void* stream) {
     g_last_error.clear();

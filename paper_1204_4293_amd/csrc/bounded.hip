@@ -100,6 +100,65 @@ k_crop2(const T* __restrict__ kE_p, const T* __restrict__ kB_p, int P, int nx, T
     if (kB) kB[o] = kB_p[i];
 }
 
+// One Philox block (8 flat pixels) per thread: rotate the shears by the
+// realisation's phases and scatter them into the P x P arrays.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rotate_scatter(const T* __restrict__ g1, const T* __restrict__ g2, int ny, int nx, int P,
+                 uint64_t seed, uint64_t r, T* __restrict__ p1, T* __restrict__ p2) {
+    const long long npix = (long long)ny * nx;
+    const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (8 * b >= npix) return;
+    uint32_t u[8];
+    philox_block_u32(seed, r, (uint64_t)b, u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const long long pix = 8 * b + i;
+        if (pix >= npix) break;
+        const int y = (int)(pix / nx), x = (int)(pix - (long long)y * nx);
+        T a = g1[pix], c = g2[pix];
+        rotate_by_u32(u[i], a, c);
+        p1[(long long)y * P + x] = a;
+        p2[(long long)y * P + x] = c;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero2(T* __restrict__ p1, T* __restrict__ p2, long long count) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    p1[i] = (T)0;
+    p2[i] = (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_welford_bc(const T* __restrict__ w, double* __restrict__ M, double* __restrict__ M2, long long count,
+             int r) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const double v = (double)w[i];
+    if (r == 0) {
+        M[i] = v;
+        M2[i] = 0.0;
+        return;
+    }
+    const double m = M[i], d = v - m, mn = m + d / (double)(r + 1);
+    M[i] = mn;
+    M2[i] = M2[i] + d * (v - mn);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sigma_snr_bc(const double* __restrict__ M2, int R, const T* __restrict__ w_signal, T* __restrict__ sigma,
+               T* __restrict__ snr, long long count) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const double sg = sqrt(M2[i] / (double)(R - 1));
+    sigma[i] = (T)sg;
+    if (snr) snr[i] = sg > 0.0 ? (T)((double)w_signal[i] / sg) : (T)0;
+}
+
 }  // namespace
 
 template <typename T>
@@ -132,6 +191,47 @@ hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* 
                 k_crop2<T><<<dim3((nx + 255) / 256, ny), 256, 0, s>>>(kE_p, kB_p, P, nx, kE, kB));
     return hipGetLastError();
 }
+
+static unsigned blocks256(long long count) { return (unsigned)((count + 255) / 256); }
+
+template <typename T>
+hipError_t launch_rotate_scatter(const T* g1, const T* g2, int ny, int nx, int P, uint64_t seed,
+                                 uint64_t r, T* p1, T* p2, hipStream_t s) {
+    const long long nblk = ((long long)ny * nx + 7) / 8;
+    AMAP_LAUNCH("rotate_scatter", s,
+                k_rotate_scatter<T><<<blocks256(nblk), 256, 0, s>>>(g1, g2, ny, nx, P, seed, r, p1, p2));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero2(T* p1, T* p2, long long count, hipStream_t s) {
+    AMAP_LAUNCH("zero", s, k_zero2<T><<<blocks256(count), 256, 0, s>>>(p1, p2, count));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_welford_bc(const T* w, double* M, double* M2, long long count, int r, hipStream_t s) {
+    AMAP_LAUNCH("welford_bc", s, k_welford_bc<T><<<blocks256(count), 256, 0, s>>>(w, M, M2, count, r));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sigma_snr_bc(const double* M2, int R, const T* w_signal, T* sigma, T* snr,
+                               long long count, hipStream_t s) {
+    AMAP_LAUNCH("sigma_snr_bc", s,
+                k_sigma_snr_bc<T><<<blocks256(count), 256, 0, s>>>(M2, R, w_signal, sigma, snr, count));
+    return hipGetLastError();
+}
+
+#define AMAP_BOUNDED_NOISE(T)                                                                            \
+    template hipError_t launch_rotate_scatter<T>(const T*, const T*, int, int, int, uint64_t, uint64_t,  \
+                                                 T*, T*, hipStream_t);                                   \
+    template hipError_t launch_zero2<T>(T*, T*, long long, hipStream_t);                                 \
+    template hipError_t launch_welford_bc<T>(const T*, double*, double*, long long, int, hipStream_t);   \
+    template hipError_t launch_sigma_snr_bc<T>(const double*, int, const T*, T*, T*, long long, hipStream_t);
+AMAP_BOUNDED_NOISE(float)
+AMAP_BOUNDED_NOISE(double)
+#undef AMAP_BOUNDED_NOISE
 
 template hipError_t launch_starlet_bc<float>(int, int, int, int, const float*, float*, float*, hipStream_t);
 template hipError_t launch_starlet_bc<double>(int, int, int, int, const double*, double*, double*,

@@ -116,3 +116,46 @@ def test_bounded_calls_reject_bad_arguments(ctx):
         ctx.ks_invert_padded(t, t, 24)          # not a power of two
     with pytest.raises(amap.AmapError):
         ctx.ks_invert_padded(t, t, 16)          # smaller than the field
+
+
+@pytest.mark.parametrize("ny,nx,P,J,R,rule,dtype", [
+    (37, 53, 64, 4, 6, amap.BC_MIRROR, torch.float32),
+    (100, 130, 256, 5, 4, amap.BC_ZERO, torch.float32),
+    (37, 53, 64, 3, 3, amap.BC_PERIODIC, torch.float64),
+    (64, 64, 64, 4, 5, amap.BC_PERIODIC, torch.float32),
+    (300, 200, 512, 6, 3, amap.BC_MIRROR, torch.float32)])
+def test_bounded_noise_maps_match_oracle(ctx, ny, nx, P, J, R, rule, dtype):
+    print("bounded noise %dx%d P=%d J=%d R=%d rule=%d %s" % (ny, nx, P, J, R, rule, dtype), flush=True)
+    n = 16
+    while n < max(ny, nx):
+        n *= 2
+    _, g1, g2 = S.shear_map(n, 90 + ny, 91 + nx)
+    g1, g2 = np.ascontiguousarray(g1[:ny, :nx]), np.ascontiguousarray(g2[:ny, :nx])
+    seed = 300 + ny
+    kE_ref, _ = O.ks_invert_padded(g1, g2, P)
+    planes_ref = O.starlet_forward_bc(kE_ref, J, rule)
+    sig_ref = O.noise_sigma_bc(g1, g2, P, J, rule, R, seed)
+    snr_ref = O.snr_planes(planes_ref, sig_ref)
+    t1, t2 = dev(g1, dtype), dev(g2, dtype)
+    planes = ctx.starlet_forward_bc(ctx.ks_invert_padded(t1, t2, P)[0], J, rule)
+    sigma, snr = ctx.noise_maps_bc(t1, t2, P, J, rule, R, seed, planes_signal=planes)
+    torch.cuda.synchronize()
+    tol = TOL[dtype] * rms(kE_ref)
+    sg, sn = sigma.double().cpu().numpy(), snr.double().cpu().numpy()
+    assert float(np.max(np.abs(sg - sig_ref))) <= tol
+    # S = w / sigma: sigma |dS| <= |dw| + |S| |dsigma| <= tol (1 + |S|)
+    assert np.all(np.abs(sn - snr_ref) * sig_ref <= tol * (1.0 + np.abs(snr_ref)) * (1 + 1e-6))
+    # sigma alone (no S/N requested)
+    s2, none = ctx.noise_maps_bc(t1, t2, P, J, rule, R, seed)
+    torch.cuda.synchronize()
+    assert none is None and torch.equal(s2, sigma)
+
+
+def test_bounded_noise_rejects_bad_arguments(ctx):
+    t = torch.zeros((20, 30), device="cuda")
+    with pytest.raises(amap.AmapError):
+        ctx.noise_maps_bc(t, t, 64, 3, amap.BC_MIRROR, 1, 0)        # one realisation
+    with pytest.raises(amap.AmapError):
+        ctx.noise_maps_bc(t, t, 16, 3, amap.BC_MIRROR, 4, 0)        # grid smaller than the field
+    with pytest.raises(amap.AmapError):
+        ctx.noise_maps_bc(t, t, 64, 3, 5, 4, 0)                     # no such rule
