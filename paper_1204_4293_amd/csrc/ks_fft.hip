@@ -619,7 +619,8 @@ __device__ __forceinline__ constexpr int pair_out(int j, int h) {
 // with y0's sign, at half of the frequencies (the low half at k2 < N2/2,
 // the high half at k2 + N2/2) and the halves exchange the values; passing
 // (V, -V) for the imaginary part hands each half its own row's sign.  The
-// result is bit for bit that of ks_multiply (the sign changes are exact).
+// factors are those ks_multiply computes, value for value (the sign changes
+// are exact).
 template <typename T, int LOGN, int SCALE_DEN>
 __device__ __forceinline__ void ks_multiply_pair(cpx<T> (&b)[FS<LOGN>::RR][FS<LOGN>::N2], int y0, int t,
                                                  bool hi) {
