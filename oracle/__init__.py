@@ -50,5 +50,5 @@ from .stats import (peak_histogram, peak_histogram_planes, plane_moments,  # noq
 from .pipeline import run_path  # noqa: F401
 from .bounded import (  # noqa: F401
     BC_PERIODIC, BC_MIRROR, BC_ZERO, boundary_index, smooth_step_bc, starlet_forward_bc,
-    even_extension, ks_invert_padded, noise_sigma_bc,
+    even_extension, ks_invert_padded, noise_sigma_bc, count_peaks_bc,
 )

@@ -23,6 +23,11 @@ the end of Sec. 5 without fixing a rule.  Readings used here:
     definition of ``oracle.rng``), and the rotated field goes through the
     same padded KS and bounded starlet as the signal; sigma_j is the
     unbiased per-pixel sample standard deviation (Welford's update);
+  * a peak of a bounded plane is a strict 8-neighbour maximum above t (as in
+    ``oracle.peaks``) with each neighbour's row and column index taken
+    through the plane's edge rule (under the zero rule a neighbour outside
+    the field has value 0; under the mirror rule an edge pixel meets its
+    inner neighbour twice);
   * KS of a bounded field: the shear is zero outside its ny x nx rectangle,
     which is placed at the origin of a P x P periodic grid (P a power of two,
     P >= max(ny, nx)); the periodic KS of ``oracle.ks`` is applied there and
@@ -41,7 +46,9 @@ with the O(N^4) brute-force DFT; the bounded noise sigma under the periodic
 rule with P = n equals ``oracle.noise.noise_sigma``, and its variance tracks
 the closed form 1/2 sum_y |gamma(y)|^2 (A1(x, y)^2 + A2(x, y)^2), A1 and A2
 the responses of w_j(x) to unit gamma1 and gamma2 at y, within chi-square
-scatter.
+scatter; bounded peak counts under the periodic rule equal
+``oracle.peaks.count_peaks``, and under every rule equal a pure-Python loop
+over pixels and neighbours.
 """
 
 import numpy as np
@@ -158,3 +165,19 @@ def noise_sigma_bc(g1, g2, P, J, mode, n_real, seed):
         mean += delta / (r + 1)
         m2 += delta * (w - mean)
     return np.sqrt(m2 / (n_real - 1))
+
+
+def count_peaks_bc(plane, t, mode):
+    """Strict 8-neighbour maxima above t of an ny x nx plane under an edge rule."""
+    p = np.asarray(plane).astype(np.float64)
+    ny, nx = p.shape
+    mask = p > float(t)
+    for dy in (-1, 0, 1):
+        iy = boundary_index(np.arange(ny) + dy, ny, mode)
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            ix = boundary_index(np.arange(nx) + dx, nx, mode)
+            q = _take(_take(p, iy, axis=0), ix, axis=1)
+            mask &= p > q
+    return int(np.count_nonzero(mask))

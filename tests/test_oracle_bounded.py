@@ -187,3 +187,56 @@ def test_bounded_noise_variance_tracks_its_expectation(mode):
     # the pixel mean of the ratio is far tighter
     assert abs(float(ratio.mean()) - 1.0) < 0.02
     assert float(np.max(np.abs(ratio - 1.0))) < 6 * np.sqrt(2.0 / (R - 1)) * 1.5
+
+
+def brute_peaks_bc(plane, t, mode):
+    ny, nx = plane.shape
+    rows = O.boundary_index(np.arange(-1, ny + 1), ny, mode)   # rows[y + 1] is row y
+    cols = O.boundary_index(np.arange(-1, nx + 1), nx, mode)
+    count = 0
+    for y in range(ny):
+        for x in range(nx):
+            v = float(plane[y, x])
+            ok = v > t
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if dy == 0 and dx == 0:
+                        continue
+                    yy, xx = int(rows[y + dy + 1]), int(cols[x + dx + 1])
+                    q = 0.0 if (yy < 0 or xx < 0) else float(plane[yy, xx])
+                    ok = ok and v > q
+            count += ok
+    return count
+
+
+@pytest.mark.parametrize("mode", [O.BC_PERIODIC, O.BC_MIRROR, O.BC_ZERO])
+def test_bounded_peaks_match_brute_force(mode):
+    rng = np.random.default_rng(50 + mode)
+    plane = rng.integers(-4, 5, size=(11, 14)).astype(np.float64) * 0.5   # ties and plateaus
+    plane += rng.standard_normal((11, 14)) * (rng.random((11, 14)) < 0.6)
+    plane[0, 0] = 9.0          # corner peak under every rule
+    plane[10, 7] = 8.0         # bottom-edge peak
+    for t in (-10.0, 0.0, 1.0):
+        assert O.count_peaks_bc(plane, t, mode) == brute_peaks_bc(plane, t, mode)
+
+
+def test_bounded_peaks_reduce_to_the_periodic_count():
+    rng = np.random.default_rng(4)
+    plane = rng.standard_normal((32, 32))
+    for t in (-1.0, 0.5, 2.0):
+        assert O.count_peaks_bc(plane, t, O.BC_PERIODIC) == O.count_peaks(plane, t)
+
+
+def test_bounded_peaks_edge_rules_differ_as_stated():
+    # a bright edge pixel is a peak under every rule; a raised edge pixel in
+    # a negative plane is one under the mirror rule but not under the zero
+    # rule, whose outside zeros are higher
+    p = np.zeros((5, 6))
+    p[2, 5] = 1.0
+    assert O.count_peaks_bc(p, 0.5, O.BC_MIRROR) == 1
+    assert O.count_peaks_bc(p, 0.5, O.BC_ZERO) == 1
+    assert O.count_peaks_bc(p, 0.5, O.BC_PERIODIC) == 1
+    q = np.full((5, 6), -1.0)
+    q[2, 5] = -0.5
+    assert O.count_peaks_bc(q, -0.9, O.BC_MIRROR) == 1
+    assert O.count_peaks_bc(q, -0.9, O.BC_ZERO) == 0     # the zeros outside are higher
