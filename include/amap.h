@@ -219,6 +219,17 @@ amap_status amap_noise_maps_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, in
                                uint64_t seed, const void* planes_signal, void* sigma, void* snr,
                                void* stream);
 
+/*
+ * Peak counts of nplanes ny x nx planes with edges (as amap_count_peaks:
+ * value > threshold and > each of its 8 neighbours, strict, in double, NaN
+ * never a peak), each neighbour's row and column taken through the edge
+ * rule `boundary` (under AMAP_BC_ZERO a neighbour outside the field is 0).
+ * counts_dev: device array of nplanes long long, overwritten.
+ */
+amap_status amap_count_peaks_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int nplanes,
+                                int boundary, const void* planes, double threshold,
+                                long long* counts_dev, void* stream);
+
 /* Exact inverse of the decomposition (Sec. 3): kappa_out = c_{J-1} + sum w_j.
  * planes: J*n*n; kappa_out: n*n (may not overlap planes). */
 amap_status amap_starlet_reconstruct(amap_ctx_t ctx, amap_dtype dt, int n, int J,

@@ -80,6 +80,7 @@ def load():
         "amap_starlet_forward_bc": (I, [P, I, I, I, I, I, P, P, P]),
         "amap_ks_invert_padded": (I, [P, I, I, I, I, P, P, P, P, P]),
         "amap_noise_maps_bc": (I, [P, I, I, I, I, I, I, P, P, I, U64, P, P, P, P]),
+        "amap_count_peaks_bc": (I, [P, I, I, I, I, I, P, D, P, P]),
         "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
         "amap_map_direct": (I, [P, I, I, P, P, D, I, D, D, P, P]),
         "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
@@ -260,6 +261,15 @@ class Context:
                                          _ptr(g1), _ptr(g2), int(n_real), int(seed),
                                          _ptr(planes_signal), _ptr(sigma), _ptr(snr), _stream()))
         return sigma, snr
+
+    def count_peaks_bc(self, planes, threshold, boundary, counts=None):
+        """Peaks above threshold of each ny x nx plane under an edge rule."""
+        nplanes, ny, nx = int(planes.shape[0]), int(planes.shape[-2]), int(planes.shape[-1])
+        if counts is None:
+            counts = torch.empty(nplanes, dtype=torch.int64, device=planes.device)
+        _check(load().amap_count_peaks_bc(self._h, _dt(planes), ny, nx, nplanes, int(boundary),
+                                          _ptr(planes), float(threshold), _ptr(counts), _stream()))
+        return counts
 
     def starlet_reconstruct(self, planes, out=None):
         J, n = planes.shape[0], _side(planes)

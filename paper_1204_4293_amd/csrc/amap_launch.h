@@ -179,6 +179,11 @@ template <typename T>
 hipError_t launch_zero2(T* p1, T* p2, long long count, hipStream_t s);
 template <typename T>
 hipError_t launch_welford_bc(const T* w, double* M, double* M2, long long count, int r, hipStream_t s);
+// Peaks above thr of nplanes ny x nx planes under an edge rule (counts:
+// nplanes long long, overwritten).
+template <typename T>
+hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes, double thr,
+                                 long long* counts, hipStream_t s);
 template <typename T>
 hipError_t launch_sigma_snr_bc(const double* M2, int R, const T* w_signal, T* sigma, T* snr,
                                long long count, hipStream_t s);

@@ -754,6 +754,33 @@ amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, i
     return AMAP_OK;
 }
 
+amap_status amap_count_peaks_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int nplanes,
+                                int boundary, const void* planes, double threshold,
+                                long long* counts_dev, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    if (ny < 2 || nx < 2 || ny > 16384 || nx > 16384)
+        return fail(AMAP_E_INVAL, "plane sides must be in [2, 16384] (got %d x %d)", ny, nx);
+    if (nplanes < 1 || nplanes > 65535)
+        return fail(AMAP_E_INVAL, "nplanes must be in [1, 65535] (got %d)", nplanes);
+    if (boundary < AMAP_BC_PERIODIC || boundary > AMAP_BC_ZERO)
+        return fail(AMAP_E_INVAL, "boundary must be AMAP_BC_PERIODIC, _MIRROR or _ZERO (got %d)", boundary);
+    AMAP_TRY(check_ptr(planes, "planes"));
+    AMAP_TRY(check_ptr(counts_dev, "counts_dev"));
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt == AMAP_F32)
+        AMAP_HIP(launch_count_peaks_bc<float>(ny, nx, nplanes, boundary, (const float*)planes, threshold,
+                                              counts_dev, s), "peak kernel");
+    else
+        AMAP_HIP(launch_count_peaks_bc<double>(ny, nx, nplanes, boundary, (const double*)planes,
+                                               threshold, counts_dev, s), "peak kernel");
+    return AMAP_OK;
+}
+
 }  // extern "C"
 
 template <typename T>

@@ -159,7 +159,61 @@ k_sigma_snr_bc(const double* __restrict__ M2, int R, const T* __restrict__ w_sig
     if (snr) snr[i] = sg > 0.0 ? (T)((double)w_signal[i] / sg) : (T)0;
 }
 
+// Strict 8-neighbour maxima above thr of ny x nx planes, neighbours taken
+// through the edge rule (0 outside under the zero rule); grid (blocks,
+// nplanes), each block striding over its plane, its count gathered in LDS
+// and added once.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double thr,
+                 long long* __restrict__ counts) {
+    __shared__ unsigned int block_count;
+    if (threadIdx.x == 0) block_count = 0u;
+    const long long npix = (long long)ny * nx;
+    const T* p = planes + (long long)blockIdx.y * npix;
+    unsigned int npk = 0;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < npix; e += (long long)gridDim.x * 256) {
+        const int y = (int)(e / nx), x = (int)(e - (long long)y * nx);
+        const T v = p[e];
+        if (!((double)v > thr)) continue;
+        bool pk = true;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = bc_index(y + dy, ny, mode);
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                const int xx = bc_index(x + dx, nx, mode);
+                const T q = (yy < 0 || xx < 0) ? (T)0 : p[(long long)yy * nx + xx];
+                pk = pk && (v > q);
+            }
+        }
+        npk += pk ? 1u : 0u;
+    }
+    __syncthreads();  // block_count is zeroed
+    if (npk) atomicAdd(&block_count, npk);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count)
+        atomicAdd((unsigned long long*)&counts[blockIdx.y], (unsigned long long)block_count);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes, double thr,
+                                 long long* counts, hipStream_t s) {
+    hipError_t e = launch_zero_i64(counts, nplanes, s);
+    if (e != hipSuccess) return e;
+    const long long chunks = ((long long)ny * nx + 255) / 256;
+    const unsigned blocks = (unsigned)(chunks < 64 ? chunks : 64);
+    AMAP_LAUNCH("count_peaks_bc", s,
+                k_count_peaks_bc<T><<<dim3(blocks, nplanes), 256, 0, s>>>(planes, ny, nx, mode, thr, counts));
+    return hipGetLastError();
+}
+template hipError_t launch_count_peaks_bc<float>(int, int, int, int, const float*, double, long long*,
+                                                 hipStream_t);
+template hipError_t launch_count_peaks_bc<double>(int, int, int, int, const double*, double, long long*,
+                                                  hipStream_t);
 
 template <typename T>
 hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T* planes, T* tmp,

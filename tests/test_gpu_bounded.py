@@ -159,3 +159,37 @@ def test_bounded_noise_rejects_bad_arguments(ctx):
         ctx.noise_maps_bc(t, t, 16, 3, amap.BC_MIRROR, 4, 0)        # grid smaller than the field
     with pytest.raises(amap.AmapError):
         ctx.noise_maps_bc(t, t, 64, 3, 5, 4, 0)                     # no such rule
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_bounded_peaks_bit_exact(ctx, rule, dtype):
+    rng = np.random.default_rng(60 + rule)
+    planes = rng.integers(-4, 5, size=(5, 77, 131)).astype(np.float64) * 0.5    # ties and plateaus
+    planes += rng.standard_normal(planes.shape) * (rng.random(planes.shape) < 0.6)
+    planes[0, 0, 0] = 9.0          # corner
+    planes[1, 76, 40] = 8.0        # bottom edge
+    planes[2, 30, 130] = 7.0       # right edge
+    planes[3, 10, 10] = np.nan
+    planes[4] = -np.abs(planes[4]) # a negative plane: zeros outside matter
+    t = dev(planes, dtype)
+    same = t.double().cpu().numpy()
+    for thr in (-10.0, -0.25, 0.0, 1.0, 3.0):
+        got = ctx.count_peaks_bc(t, thr, rule).cpu().numpy()
+        ref = [O.count_peaks_bc(pl, thr, rule) for pl in same]
+        assert [int(v) for v in got] == ref, (thr, rule)
+
+
+def test_bounded_path_peaks_on_its_snr(ctx):
+    # the bounded path end to end on a 300 x 200 field: its S/N planes' peak
+    # counts equal the oracle's count on the same planes
+    ny, nx, P, J, R, rule = 300, 200, 512, 6, 4, amap.BC_MIRROR
+    _, g1, g2 = S.shear_map(512, 123, 124)
+    t1 = dev(np.ascontiguousarray(g1[:ny, :nx]), torch.float32)
+    t2 = dev(np.ascontiguousarray(g2[:ny, :nx]), torch.float32)
+    planes = ctx.starlet_forward_bc(ctx.ks_invert_padded(t1, t2, P)[0], J, rule)
+    _, snr = ctx.noise_maps_bc(t1, t2, P, J, rule, R, 9, planes_signal=planes)
+    got = ctx.count_peaks_bc(snr, 2.5, rule).cpu().numpy()
+    same = snr.double().cpu().numpy()
+    assert [int(v) for v in got] == [O.count_peaks_bc(pl, 2.5, rule) for pl in same]
+    assert sum(int(v) for v in got) > 0
