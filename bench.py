@@ -20,7 +20,8 @@ Printed as one JSON line.  Extra objects:
                with J = log2 theta + 1 on the 1024^2 map (the paper's comparison)
   bounded      a 1000 x 1000 field with edges (a crop of the map): KS of the
                field zero-extended into a 2048^2 grid + starlet J = 7 under the
-               mirror edge rule
+               mirror edge rule; and its noise sigma, S/N and peaks from 16
+               realisations (one launch sequence per realisation)
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
@@ -508,9 +509,26 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     t_b = ev0.elapsed_time(ev1) / 20
+    RB_REAL = 16
+    bpk = torch.empty(J - 1, dtype=torch.int64, device=dev)
+
+    def bounded_noise():
+        _, snr_b = ctx.noise_maps_bc(b1, b2, PB, J, amap.BC_MIRROR, RB_REAL, 7, planes_signal=bpl)
+        ctx.count_peaks_bc(snr_b, 3.0, amap.BC_MIRROR, counts=bpk)
+    bounded_noise()
+    torch.cuda.synchronize()
+    ev0.record()
+    bounded_noise()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_bn = ev0.elapsed_time(ev1)
     bounded = {"workload": "1000x1000 float32 field (corner of the step's map), KS zero-extended "
                            "into 2048x2048, starlet J=7, mirror edges",
-               "ms_per_map": t_b, "value": NB * NB * J / (t_b * 1e3), "unit": "Mpix·scales/s"}
+               "ms_per_map": t_b, "value": NB * NB * J / (t_b * 1e3), "unit": "Mpix·scales/s",
+               "noise": {"n_real": RB_REAL, "ms": t_bn, "ms_per_realisation": t_bn / RB_REAL,
+                         "value": (1 + RB_REAL) * NB * NB * J / ((t_b + t_bn) * 1e3),
+                         "unit": "Mpix·scales/s", "what": "sigma, S/N and peaks (S/N > 3), signal "
+                                                          "pass included in value"}}
 
     batched = served = None
     if not args.no_batched:
