@@ -161,10 +161,10 @@ k_sigma_snr_bc(const double* __restrict__ M2, int R, const T* __restrict__ w_sig
 
 // Strict 8-neighbour maxima above thr of ny x nx planes, neighbours taken
 // through the edge rule (0 outside under the zero rule); grid (blocks,
-// nplanes), each block striding over its plane, its count gathered in LDS
-// and added once.
+// nplanes) of 1024 threads, each block taking rows of its plane in turn,
+// its count gathered in LDS and added once.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double thr,
                  long long* __restrict__ counts) {
     __shared__ unsigned int block_count;
@@ -172,23 +172,24 @@ k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double 
     const long long npix = (long long)ny * nx;
     const T* p = planes + (long long)blockIdx.y * npix;
     unsigned int npk = 0;
-    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < npix; e += (long long)gridDim.x * 256) {
-        const int y = (int)(e / nx), x = (int)(e - (long long)y * nx);
-        const T v = p[e];
-        if (!((double)v > thr)) continue;
-        bool pk = true;
+    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+        for (int x = threadIdx.x; x < nx; x += 1024) {
+            const T v = p[(long long)y * nx + x];
+            if (!((double)v > thr)) continue;
+            bool pk = true;
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = bc_index(y + dy, ny, mode);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = bc_index(y + dy, ny, mode);
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dy == 0 && dx == 0) continue;
-                const int xx = bc_index(x + dx, nx, mode);
-                const T q = (yy < 0 || xx < 0) ? (T)0 : p[(long long)yy * nx + xx];
-                pk = pk && (v > q);
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dy == 0 && dx == 0) continue;
+                    const int xx = bc_index(x + dx, nx, mode);
+                    const T q = (yy < 0 || xx < 0) ? (T)0 : p[(long long)yy * nx + xx];
+                    pk = pk && (v > q);
+                }
             }
+            npk += pk ? 1u : 0u;
         }
-        npk += pk ? 1u : 0u;
     }
     __syncthreads();  // block_count is zeroed
     if (npk) atomicAdd(&block_count, npk);
@@ -204,10 +205,9 @@ hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T*
                                  long long* counts, hipStream_t s) {
     hipError_t e = launch_zero_i64(counts, nplanes, s);
     if (e != hipSuccess) return e;
-    const long long chunks = ((long long)ny * nx + 255) / 256;
-    const unsigned blocks = (unsigned)(chunks < 64 ? chunks : 64);
+    const unsigned blocks = (unsigned)(ny < 256 ? ny : 256);  // at most 256 adds per counter
     AMAP_LAUNCH("count_peaks_bc", s,
-                k_count_peaks_bc<T><<<dim3(blocks, nplanes), 256, 0, s>>>(planes, ny, nx, mode, thr, counts));
+                k_count_peaks_bc<T><<<dim3(blocks, nplanes), 1024, 0, s>>>(planes, ny, nx, mode, thr, counts));
     return hipGetLastError();
 }
 template hipError_t launch_count_peaks_bc<float>(int, int, int, int, const float*, double, long long*,
