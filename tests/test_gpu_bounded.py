@@ -45,7 +45,7 @@ def field(ny, nx, seed):
 
 
 @pytest.mark.parametrize("ny,nx,J", [(16, 16, 3), (37, 53, 5), (100, 257, 6), (2, 2, 3),
-                                     (3, 700, 7), (1000, 1000, 7)])
+                                     (3, 700, 7), (5, 9, 16), (1000, 1000, 7)])
 @pytest.mark.parametrize("rule", RULES)
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_bounded_starlet_matches_oracle(ctx, ny, nx, J, rule, dtype):
@@ -123,7 +123,8 @@ def test_bounded_calls_reject_bad_arguments(ctx):
     (100, 130, 256, 5, 4, amap.BC_ZERO, torch.float32),
     (37, 53, 64, 3, 3, amap.BC_PERIODIC, torch.float64),
     (64, 64, 64, 4, 5, amap.BC_PERIODIC, torch.float32),
-    (300, 200, 512, 6, 3, amap.BC_MIRROR, torch.float32)])
+    (300, 200, 512, 6, 3, amap.BC_MIRROR, torch.float32),
+    (2, 2, 16, 3, 2, amap.BC_ZERO, torch.float64)])
 def test_bounded_noise_maps_match_oracle(ctx, ny, nx, P, J, R, rule, dtype):
     print("bounded noise %dx%d P=%d J=%d R=%d rule=%d %s" % (ny, nx, P, J, R, rule, dtype), flush=True)
     n = 16
