@@ -21,7 +21,7 @@ Printed as one JSON line.  Extra objects:
   bounded      a 1000 x 1000 field with edges (a crop of the map): KS of the
                field zero-extended into a 2048^2 grid + starlet J = 7 under the
                mirror edge rule; and its noise sigma, S/N and peaks from 16
-               realisations (one launch sequence per realisation)
+               realisations
   roofline     the dominant kernel, timed with HIP events on its stream
   kernels      per-kernel launches and average microseconds
   cpu_baseline the FP64 oracle on a bounded sample of the same workload

@@ -212,7 +212,8 @@ amap_status amap_ks_invert_padded(amap_ctx_t ctx, amap_dtype dt, int ny, int nx,
  * in double, Welford's update).  If snr is not NULL, planes_signal (J*ny*nx,
  * the signal's planes from the same two calls) must be given and
  * snr_j = w_j / sigma_j (0 where sigma_j = 0).  sigma, snr: (J-1)*ny*nx.
- * Sides >= 2 and <= P; n_real >= 2.  One launch sequence per realisation.
+ * Sides >= 2 and <= P; n_real >= 2.  Realisations run in batches sized to
+ * about 1 GiB of the context's workspace (at least one).
  */
 amap_status amap_noise_maps_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int P, int J,
                                int boundary, const void* g1, const void* g2, int n_real,

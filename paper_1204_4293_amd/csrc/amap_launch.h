@@ -150,35 +150,41 @@ template <typename T>
 hipError_t launch_map_direct(int logn, const T* g1, const T* g2, int R, const int* half,
                              const T* wc, const T* ws, T* out, hipStream_t s);
 
-// Starlet of an ny x nx field (any sizes >= 2) under a boundary rule
+// Starlet of `maps` ny x nx fields (any sizes >= 2) under a boundary rule
 // (0 periodic, 1 mirror: whole-sample symmetric, 2 zero outside): J planes
-// w_1 .. w_{J-1}, c_{J-1}, each ny*nx, in `planes`; `tmp` holds ny*nx.
+// w_1 .. w_{J-1}, c_{J-1}, each ny*nx; map m's image at image + m
+// image_stride, its planes at planes + m planes_stride; `tmp` holds
+// maps*ny*nx.
 template <typename T>
 hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T* planes, T* tmp,
-                             hipStream_t s);
+                             int maps, long long image_stride, long long planes_stride, hipStream_t s);
 
 // Zero extension of an ny x nx pair of fields into P x P arrays, and the
-// ny x nx rectangle of P x P arrays read back (kB_p/kB may be null).
+// ny x nx rectangles of `maps` P x P arrays (in_stride apart) read back
+// (out_stride apart; kB_p/kB may be null).
 template <typename T>
 hipError_t launch_pad2(const T* g1, const T* g2, int ny, int nx, int P, T* p1, T* p2, hipStream_t s);
 template <typename T>
-hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB,
-                        hipStream_t s);
+hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB, int maps,
+                        long long in_stride, long long out_stride, hipStream_t s);
 
 // Noise realisations of a bounded field: the ny x nx shears rotated by the
-// Philox phases of realisation r (flat pixel index y*nx + x) and written
-// into the field's rectangle of the P x P arrays p1, p2 (their rest is left
-// as it is: cleared once by launch_zero2); Welford's update of the running
-// mean M and squared deviations M2 (double, `count` elements) with the r-th
-// value w (r = 0 writes them unread); sigma = sqrt(M2/(R-1)) and, if snr is
-// not null, snr = w_signal / sigma (0 where sigma = 0).
+// Philox phases of realisations r0 .. r0+nb-1 (flat pixel index y*nx + x)
+// and written into the field's rectangle of each realisation's P x P
+// arrays (p_stride apart; their rest is left as it is: cleared once by
+// launch_zero2); Welford's update of the running mean M and squared
+// deviations M2 (double, `count` elements) with the values of realisations
+// r0 .. r0+nb-1 in order, w_stride apart (realisation 0 writes them unread);
+// sigma = sqrt(M2/(R-1)) and, if snr is not null, snr = w_signal / sigma (0
+// where sigma = 0).
 template <typename T>
 hipError_t launch_rotate_scatter(const T* g1, const T* g2, int ny, int nx, int P, uint64_t seed,
-                                 uint64_t r, T* p1, T* p2, hipStream_t s);
+                                 uint64_t r0, int nb, T* p1, T* p2, long long p_stride, hipStream_t s);
 template <typename T>
 hipError_t launch_zero2(T* p1, T* p2, long long count, hipStream_t s);
 template <typename T>
-hipError_t launch_welford_bc(const T* w, double* M, double* M2, long long count, int r, hipStream_t s);
+hipError_t launch_welford_bc(const T* w, long long w_stride, int nb, double* M, double* M2,
+                             long long count, int r0, hipStream_t s);
 // Peaks above thr of nplanes ny x nx planes under an edge rule (counts:
 // nplanes long long, overwritten).
 template <typename T>

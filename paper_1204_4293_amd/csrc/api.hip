@@ -700,10 +700,10 @@ amap_status amap_starlet_forward_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx,
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dt == AMAP_F32)
         AMAP_HIP(launch_starlet_bc<float>(ny, nx, J, boundary, (const float*)image, (float*)planes,
-                                          (float*)c->ws.ptr, s), "bounded starlet kernels");
+                                          (float*)c->ws.ptr, 1, 0, 0, s), "bounded starlet kernels");
     else
         AMAP_HIP(launch_starlet_bc<double>(ny, nx, J, boundary, (const double*)image, (double*)planes,
-                                           (double*)c->ws.ptr, s), "bounded starlet kernels");
+                                           (double*)c->ws.ptr, 1, 0, 0, s), "bounded starlet kernels");
     return AMAP_OK;
 }
 
@@ -740,7 +740,8 @@ amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, i
         AMAP_HIP(launch_pad2<float>((const float*)g1, (const float*)g2, ny, nx, P, p1, p2, s), "pad kernel");
         AMAP_TRY(enqueue_ks<float>(c, logn, 1, p1, p2, 0, (cpx<float>*)w, e, b, (long long)P * P,
                                    false, 0, 0, s));
-        AMAP_HIP(launch_crop2<float>(e, b, P, ny, nx, (float*)kappa_e, (float*)kappa_b, s), "crop kernel");
+        AMAP_HIP(launch_crop2<float>(e, b, P, ny, nx, (float*)kappa_e, (float*)kappa_b, 1, 0, 0, s),
+                 "crop kernel");
     } else {
         double *p1 = (double*)(w + 2 * pb), *p2 = (double*)(w + 3 * pb);
         double *e = (double*)(w + 4 * pb), *b = kappa_b ? (double*)(w + 5 * pb) : nullptr;
@@ -748,7 +749,7 @@ amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, i
                  "pad kernel");
         AMAP_TRY(enqueue_ks<double>(c, logn, 1, p1, p2, 0, (cpx<double>*)w, e, b, (long long)P * P,
                                     false, 0, 0, s));
-        AMAP_HIP(launch_crop2<double>(e, b, P, ny, nx, (double*)kappa_e, (double*)kappa_b, s),
+        AMAP_HIP(launch_crop2<double>(e, b, P, ny, nx, (double*)kappa_e, (double*)kappa_b, 1, 0, 0, s),
                  "crop kernel");
     }
     return AMAP_OK;
@@ -783,33 +784,53 @@ amap_status amap_count_peaks_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int
 
 }  // extern "C"
 
+// Realisations per launch of the bounded noise path: as many as fit about
+// 1 GiB of workspace (P^2 spectrum, padded shears and kappa per
+// realisation, plus its field-sized kappa, scratch and planes), 1 .. 32.
+static int bounded_noise_batch(int ny, int nx, int P, int J, size_t esz, int n_real) {
+    const size_t per = 5 * (size_t)P * P * esz + (size_t)(2 + J) * ny * nx * esz;
+    size_t b = ((size_t)1 << 30) / per;
+    if (b < 1) b = 1;
+    if (b > 32) b = 32;
+    if (b > (size_t)n_real) b = (size_t)n_real;
+    return (int)b;
+}
+static size_t bounded_noise_bytes(int ny, int nx, int P, int J, size_t esz, int B) {
+    const size_t pp = (size_t)P * P * esz * B, ff = (size_t)ny * nx * esz * B;
+    return align256(2 * pp) + 3 * align256(pp) + 2 * align256(ff) + align256(ff * J) +
+           2 * align256((size_t)(J - 1) * ny * nx * 8);
+}
+
 template <typename T>
 static amap_status enqueue_noise_bc(const amap_ctx* c, char* w, int ny, int nx, int P, int J,
                                     int boundary, const T* g1, const T* g2, int n_real, uint64_t seed,
                                     const T* planes_signal, T* sigma, T* snr, hipStream_t s) {
-    const size_t esz = sizeof(T);
-    const size_t pb = align256((size_t)P * P * esz), fb = align256((size_t)ny * nx * esz);
-    const long long cnt = (long long)(J - 1) * ny * nx;
+    const int B = bounded_noise_batch(ny, nx, P, J, sizeof(T), n_real);
+    const long long pn = (long long)P * P, fn = (long long)ny * nx;
+    const size_t pp = (size_t)pn * sizeof(T) * B, ff = (size_t)fn * sizeof(T) * B;
+    const long long cnt = (long long)(J - 1) * fn;
     char* q = w;
-    cpx<T>* C = reinterpret_cast<cpx<T>*>(q);  q += 2 * pb;
-    T* p1 = reinterpret_cast<T*>(q);           q += pb;
-    T* p2 = reinterpret_cast<T*>(q);           q += pb;
-    T* ke = reinterpret_cast<T*>(q);           q += pb;
-    T* kap = reinterpret_cast<T*>(q);          q += fb;
-    T* tmp = reinterpret_cast<T*>(q);          q += fb;
-    T* pl = reinterpret_cast<T*>(q);           q += align256((size_t)J * ny * nx * esz);
+    cpx<T>* C = reinterpret_cast<cpx<T>*>(q);  q += align256(2 * pp);
+    T* p1 = reinterpret_cast<T*>(q);           q += align256(pp);
+    T* p2 = reinterpret_cast<T*>(q);           q += align256(pp);
+    T* ke = reinterpret_cast<T*>(q);           q += align256(pp);
+    T* kap = reinterpret_cast<T*>(q);          q += align256(ff);
+    T* tmp = reinterpret_cast<T*>(q);          q += align256(ff);
+    T* pl = reinterpret_cast<T*>(q);           q += align256(ff * J);
     double* M = reinterpret_cast<double*>(q);  q += align256((size_t)cnt * 8);
     double* M2 = reinterpret_cast<double*>(q);
-    // the grid outside the field stays zero: the KS never writes its inputs
-    AMAP_HIP(launch_zero2<T>(p1, p2, (long long)P * P, s), "zero kernel");
-    for (int r = 0; r < n_real; ++r) {
-        AMAP_HIP(launch_rotate_scatter<T>(g1, g2, ny, nx, P, seed, (uint64_t)r, p1, p2, s),
+    // the grids outside the field stay zero: the KS never writes its inputs
+    AMAP_HIP(launch_zero2<T>(p1, p2, pn * B, s), "zero kernel");
+    for (int r0 = 0; r0 < n_real; r0 += B) {
+        const int nb = n_real - r0 < B ? n_real - r0 : B;
+        AMAP_HIP(launch_rotate_scatter<T>(g1, g2, ny, nx, P, seed, (uint64_t)r0, nb, p1, p2, pn, s),
                  "rotation kernel");
-        AMAP_TRY(enqueue_ks<T>(c, ilog2(P), 1, p1, p2, 0, C, ke, nullptr, (long long)P * P, false, 0,
-                               0, s));
-        AMAP_HIP(launch_crop2<T>(ke, nullptr, P, ny, nx, kap, nullptr, s), "crop kernel");
-        AMAP_HIP(launch_starlet_bc<T>(ny, nx, J, boundary, kap, pl, tmp, s), "bounded starlet kernels");
-        AMAP_HIP(launch_welford_bc<T>(pl, M, M2, cnt, r, s), "statistics kernel");
+        AMAP_TRY(enqueue_ks<T>(c, ilog2(P), nb, p1, p2, pn, C, ke, nullptr, pn, false, 0, 0, s,
+                               /*pair_e=*/true));
+        AMAP_HIP(launch_crop2<T>(ke, nullptr, P, ny, nx, kap, nullptr, nb, pn, fn, s), "crop kernel");
+        AMAP_HIP(launch_starlet_bc<T>(ny, nx, J, boundary, kap, pl, tmp, nb, fn, (long long)J * fn, s),
+                 "bounded starlet kernels");
+        AMAP_HIP(launch_welford_bc<T>(pl, (long long)J * fn, nb, M, M2, cnt, r0, s), "statistics kernel");
     }
     AMAP_HIP(launch_sigma_snr_bc<T>(M2, n_real, planes_signal, sigma, snr, cnt, s), "sigma kernel");
     return AMAP_OK;
@@ -845,8 +866,8 @@ amap_status amap_noise_maps_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int 
     DeviceGuard g(c->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
     TimerScope ts(c);
-    const size_t pb = align256((size_t)P * P * esize(dt)), fb = align256(f);
-    AMAP_TRY(c->ws.reserve(5 * pb + 2 * fb + align256(f * J) + 2 * align256((size_t)(J - 1) * ny * nx * 8)));
+    const int B = bounded_noise_batch(ny, nx, P, J, esize(dt), n_real);
+    AMAP_TRY(c->ws.reserve(bounded_noise_bytes(ny, nx, P, J, esize(dt), B)));
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(c->ws.ptr);
     if (dt == AMAP_F32)

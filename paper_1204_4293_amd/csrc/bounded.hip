@@ -39,12 +39,16 @@ __device__ __forceinline__ T b3(T a0, T a1, T a2, T a3, T a4) {
     return (T)0.0625 * (a0 + a4) + (T)0.25 * (a1 + a3) + (T)0.375 * a2;
 }
 
-// r[y][x] = sum_t h_t c[y][x + (t-2) d]; grid (ceil(nx/256), ny)
+// r[y][x] = sum_t h_t c[y][x + (t-2) d]; grid (ceil(nx/256), ny, maps),
+// map z at c + z c_stride and r + z r_stride
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_bc_row(const T* __restrict__ c, T* __restrict__ r, int nx, int d, int mode) {
+k_bc_row(const T* __restrict__ c, T* __restrict__ r, int nx, int d, int mode, long long c_stride,
+         long long r_stride) {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
+    c += blockIdx.z * c_stride;
+    r += blockIdx.z * r_stride;
     const T* row = c + (long long)y * nx;
     T v[5];
 #pragma unroll
@@ -57,13 +61,18 @@ k_bc_row(const T* __restrict__ c, T* __restrict__ r, int nx, int d, int mode) {
 
 // c_next[y][x] = sum_t h_t r[y + (t-2) d][x], w = c_prev - c_next.  c_prev
 // and c_next may be the same array: each thread reads and writes only its
-// own pixel of them.  grid (ceil(nx/256), ny)
+// own pixel of them.  grid (ceil(nx/256), ny, maps); map z's w and c_next
+// at + z pl_stride
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bc_col(const T* __restrict__ r, const T* c_prev, T* __restrict__ w, T* c_next, int ny, int nx,
-         int d, int mode) {
+         int d, int mode, long long r_stride, long long cp_stride, long long pl_stride) {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
+    r += blockIdx.z * r_stride;
+    c_prev += blockIdx.z * cp_stride;
+    w += blockIdx.z * pl_stride;
+    c_next += blockIdx.z * pl_stride;
     T v[5];
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
@@ -89,28 +98,34 @@ k_pad2(const T* __restrict__ g1, const T* __restrict__ g2, int ny, int nx, int P
     p2[o] = in ? g2[i] : (T)0;
 }
 
+// grid (ceil(nx/256), ny, maps): map z of P x P arrays at + z in_stride,
+// of the ny x nx outputs at + z out_stride
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_crop2(const T* __restrict__ kE_p, const T* __restrict__ kB_p, int P, int nx, T* __restrict__ kE,
-        T* __restrict__ kB) {
+        T* __restrict__ kB, long long in_stride, long long out_stride) {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
-    const long long o = (long long)y * nx + x, i = (long long)y * P + x;
+    const long long o = blockIdx.z * out_stride + (long long)y * nx + x;
+    const long long i = blockIdx.z * in_stride + (long long)y * P + x;
     kE[o] = kE_p[i];
     if (kB) kB[o] = kB_p[i];
 }
 
 // One Philox block (8 flat pixels) per thread: rotate the shears by the
-// realisation's phases and scatter them into the P x P arrays.
+// phases of realisation r0 + blockIdx.y and scatter them into that
+// realisation's P x P arrays (at + blockIdx.y p_stride).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_rotate_scatter(const T* __restrict__ g1, const T* __restrict__ g2, int ny, int nx, int P,
-                 uint64_t seed, uint64_t r, T* __restrict__ p1, T* __restrict__ p2) {
+                 uint64_t seed, uint64_t r0, T* __restrict__ p1, T* __restrict__ p2, long long p_stride) {
     const long long npix = (long long)ny * nx;
     const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
     if (8 * b >= npix) return;
+    p1 += blockIdx.y * p_stride;
+    p2 += blockIdx.y * p_stride;
     uint32_t u[8];
-    philox_block_u32(seed, r, (uint64_t)b, u);
+    philox_block_u32(seed, r0 + blockIdx.y, (uint64_t)b, u);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const long long pix = 8 * b + i;
@@ -131,21 +146,29 @@ __global__ void __launch_bounds__(256) k_zero2(T* __restrict__ p1, T* __restrict
     p2[i] = (T)0;
 }
 
+// Welford's update with realisations r0 .. r0+nb-1 in order, the b-th's
+// values at w + b w_stride (realisation 0 writes M and M2 unread).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_welford_bc(const T* __restrict__ w, double* __restrict__ M, double* __restrict__ M2, long long count,
-             int r) {
+k_welford_bc(const T* __restrict__ w, long long w_stride, int nb, double* __restrict__ M,
+             double* __restrict__ M2, long long count, int r0) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
-    const double v = (double)w[i];
-    if (r == 0) {
-        M[i] = v;
-        M2[i] = 0.0;
-        return;
+    double m = r0 == 0 ? 0.0 : M[i], m2 = r0 == 0 ? 0.0 : M2[i];
+    for (int b = 0; b < nb; ++b) {
+        const double v = (double)w[b * w_stride + i];
+        const int r = r0 + b;
+        if (r == 0) {
+            m = v;
+            m2 = 0.0;
+            continue;
+        }
+        const double d = v - m, mn = m + d / (double)(r + 1);
+        m2 = m2 + d * (v - mn);
+        m = mn;
     }
-    const double m = M[i], d = v - m, mn = m + d / (double)(r + 1);
-    M[i] = mn;
-    M2[i] = M2[i] + d * (v - mn);
+    M[i] = m;
+    M2[i] = m2;
 }
 
 template <typename T>
@@ -217,17 +240,20 @@ template hipError_t launch_count_peaks_bc<double>(int, int, int, int, const doub
 
 template <typename T>
 hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T* planes, T* tmp,
-                             hipStream_t s) {
+                             int maps, long long image_stride, long long planes_stride, hipStream_t s) {
     const long long plane = (long long)ny * nx;
     T* coarse = planes + (long long)(J - 1) * plane;
-    const dim3 grid((nx + 255) / 256, ny);
+    const dim3 grid((nx + 255) / 256, ny, maps);
     for (int j = 1; j < J; ++j) {
         const int d = 1 << (j - 1);
         const T* c_prev = j == 1 ? image : coarse;
-        AMAP_LAUNCH("starlet_bc_row", s, k_bc_row<T><<<grid, 256, 0, s>>>(c_prev, tmp, nx, d, mode));
+        const long long cp_stride = j == 1 ? image_stride : planes_stride;
+        AMAP_LAUNCH("starlet_bc_row", s,
+                    k_bc_row<T><<<grid, 256, 0, s>>>(c_prev, tmp, nx, d, mode, cp_stride, plane));
         AMAP_LAUNCH("starlet_bc_col", s,
                     k_bc_col<T><<<grid, 256, 0, s>>>(tmp, c_prev, planes + (long long)(j - 1) * plane,
-                                                     coarse, ny, nx, d, mode));
+                                                     coarse, ny, nx, d, mode, plane, cp_stride,
+                                                     planes_stride));
     }
     return hipGetLastError();
 }
@@ -239,10 +265,11 @@ hipError_t launch_pad2(const T* g1, const T* g2, int ny, int nx, int P, T* p1, T
 }
 
 template <typename T>
-hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB,
-                        hipStream_t s) {
+hipError_t launch_crop2(const T* kE_p, const T* kB_p, int P, int ny, int nx, T* kE, T* kB, int maps,
+                        long long in_stride, long long out_stride, hipStream_t s) {
     AMAP_LAUNCH("crop", s,
-                k_crop2<T><<<dim3((nx + 255) / 256, ny), 256, 0, s>>>(kE_p, kB_p, P, nx, kE, kB));
+                k_crop2<T><<<dim3((nx + 255) / 256, ny, maps), 256, 0, s>>>(kE_p, kB_p, P, nx, kE, kB,
+                                                                           in_stride, out_stride));
     return hipGetLastError();
 }
 
@@ -250,10 +277,11 @@ static unsigned blocks256(long long count) { return (unsigned)((count + 255) / 2
 
 template <typename T>
 hipError_t launch_rotate_scatter(const T* g1, const T* g2, int ny, int nx, int P, uint64_t seed,
-                                 uint64_t r, T* p1, T* p2, hipStream_t s) {
+                                 uint64_t r0, int nb, T* p1, T* p2, long long p_stride, hipStream_t s) {
     const long long nblk = ((long long)ny * nx + 7) / 8;
     AMAP_LAUNCH("rotate_scatter", s,
-                k_rotate_scatter<T><<<blocks256(nblk), 256, 0, s>>>(g1, g2, ny, nx, P, seed, r, p1, p2));
+                k_rotate_scatter<T><<<dim3(blocks256(nblk), nb), 256, 0, s>>>(g1, g2, ny, nx, P, seed, r0,
+                                                                              p1, p2, p_stride));
     return hipGetLastError();
 }
 
@@ -264,8 +292,10 @@ hipError_t launch_zero2(T* p1, T* p2, long long count, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_welford_bc(const T* w, double* M, double* M2, long long count, int r, hipStream_t s) {
-    AMAP_LAUNCH("welford_bc", s, k_welford_bc<T><<<blocks256(count), 256, 0, s>>>(w, M, M2, count, r));
+hipError_t launch_welford_bc(const T* w, long long w_stride, int nb, double* M, double* M2,
+                             long long count, int r0, hipStream_t s) {
+    AMAP_LAUNCH("welford_bc", s,
+                k_welford_bc<T><<<blocks256(count), 256, 0, s>>>(w, w_stride, nb, M, M2, count, r0));
     return hipGetLastError();
 }
 
@@ -279,24 +309,26 @@ hipError_t launch_sigma_snr_bc(const double* M2, int R, const T* w_signal, T* si
 
 #define AMAP_BOUNDED_NOISE(T)                                                                            \
     template hipError_t launch_rotate_scatter<T>(const T*, const T*, int, int, int, uint64_t, uint64_t,  \
-                                                 T*, T*, hipStream_t);                                   \
+                                                 int, T*, T*, long long, hipStream_t);                   \
     template hipError_t launch_zero2<T>(T*, T*, long long, hipStream_t);                                 \
-    template hipError_t launch_welford_bc<T>(const T*, double*, double*, long long, int, hipStream_t);   \
+    template hipError_t launch_welford_bc<T>(const T*, long long, int, double*, double*, long long, int, \
+                                             hipStream_t);                                               \
     template hipError_t launch_sigma_snr_bc<T>(const double*, int, const T*, T*, T*, long long, hipStream_t);
 AMAP_BOUNDED_NOISE(float)
 AMAP_BOUNDED_NOISE(double)
 #undef AMAP_BOUNDED_NOISE
 
-template hipError_t launch_starlet_bc<float>(int, int, int, int, const float*, float*, float*, hipStream_t);
-template hipError_t launch_starlet_bc<double>(int, int, int, int, const double*, double*, double*,
-                                              hipStream_t);
+template hipError_t launch_starlet_bc<float>(int, int, int, int, const float*, float*, float*, int,
+                                             long long, long long, hipStream_t);
+template hipError_t launch_starlet_bc<double>(int, int, int, int, const double*, double*, double*, int,
+                                              long long, long long, hipStream_t);
 template hipError_t launch_pad2<float>(const float*, const float*, int, int, int, float*, float*,
                                        hipStream_t);
 template hipError_t launch_pad2<double>(const double*, const double*, int, int, int, double*, double*,
                                         hipStream_t);
-template hipError_t launch_crop2<float>(const float*, const float*, int, int, int, float*, float*,
-                                        hipStream_t);
+template hipError_t launch_crop2<float>(const float*, const float*, int, int, int, float*, float*, int,
+                                        long long, long long, hipStream_t);
 template hipError_t launch_crop2<double>(const double*, const double*, int, int, int, double*, double*,
-                                         hipStream_t);
+                                         int, long long, long long, hipStream_t);
 
 }  // namespace amap
