@@ -124,7 +124,8 @@ def test_bounded_calls_reject_bad_arguments(ctx):
     (37, 53, 64, 3, 3, amap.BC_PERIODIC, torch.float64),
     (64, 64, 64, 4, 5, amap.BC_PERIODIC, torch.float32),
     (300, 200, 512, 6, 3, amap.BC_MIRROR, torch.float32),
-    (2, 2, 16, 3, 2, amap.BC_ZERO, torch.float64)])
+    (2, 2, 16, 3, 2, amap.BC_ZERO, torch.float64),
+    (300, 200, 512, 4, 35, amap.BC_MIRROR, torch.float32)])   # 32 + 3 realisations per batch
 def test_bounded_noise_maps_match_oracle(ctx, ny, nx, P, J, R, rule, dtype):
     print("bounded noise %dx%d P=%d J=%d R=%d rule=%d %s" % (ny, nx, P, J, R, rule, dtype), flush=True)
     n = 16
