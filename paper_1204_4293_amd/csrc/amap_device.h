@@ -18,6 +18,22 @@ struct cpx {
 
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> make_cpx(T a, T b) { cpx<T> r; r.x = a; r.y = b; return r; }
+
+// Streaming stores for outputs that the next kernel reads back from memory:
+// marked non-temporal, so they do not displace cached inputs and leave no
+// dirty lines in L2 for the consumer to contend with.
+__device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(cpx<float>* p, const cpx<float>& v) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f2*>(p));
+}
+__device__ __forceinline__ void store_stream(cpx<double>* p, const cpx<double>& v) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<d2*>(p));
+}
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return make_cpx(a.x + b.x, a.y + b.y); }
 template <typename T>

@@ -389,7 +389,7 @@ k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_st
         for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(k1 * N2 + n2) * W + c];
         dft_reg<T, N2, false>(v);
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) out[(long long)(k1 + N1 * k2) * N] = v[k2];
+        for (int k2 = 0; k2 < N2; ++k2) store_stream(&out[(long long)(k1 + N1 * k2) * N], v[k2]);
     }
 }
 
