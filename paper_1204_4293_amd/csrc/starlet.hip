@@ -88,6 +88,15 @@ __device__ __forceinline__ void vstore(T* p, const VArr<T, G>& r) {
     for (int c = 0; c < G; ++c) v[c] = r.e[c];
     *reinterpret_cast<typename Vec<T>::type*>(p) = v;
 }
+// The same store marked non-temporal, for coarse planes that the next stage
+// reads back from memory (keeps them from displacing cached inputs).
+template <typename T, int G>
+__device__ __forceinline__ void vstore_stream(T* p, const VArr<T, G>& r) {
+    typename Vec<T>::type v;
+#pragma unroll
+    for (int c = 0; c < G; ++c) v[c] = r.e[c];
+    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<T>::type*>(p));
+}
 template <typename T, int G>
 __device__ __forceinline__ VArr<T, G> vcombine(const VArr<T, G>& a0, const VArr<T, G>& a1,
                                                const VArr<T, G>& a2, const VArr<T, G>& a3,
@@ -507,12 +516,12 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                 T* dst = a.cout + (long long)b * n2;
                 const long long gi = owned_global(g, own_e[k]);
                 if constexpr (!SG) {
-                    vstore<T, G>(dst + gi, keep[t][k]);
+                    vstore_stream<T, G>(dst + gi, keep[t][k]);
                 } else if (sg_vec) {
                     int pv, xr;
                     sg_pos(own_e[k], pv, xr);
-                    vstore<T, G>(dst + subgrid_index(out_row(g, pv) + g.x0 + xr, a.logn, a.cout_logd),
-                                 keep[t][k]);
+                    vstore_stream<T, G>(dst + subgrid_index(out_row(g, pv) + g.x0 + xr, a.logn, a.cout_logd),
+                                        keep[t][k]);
                 } else {
 #pragma unroll
                     for (int c = 0; c < G; ++c) dst[subgrid_index(gi + c, a.logn, a.cout_logd)] = keep[t][k].e[c];
