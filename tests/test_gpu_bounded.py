@@ -195,3 +195,20 @@ def test_bounded_path_peaks_on_its_snr(ctx):
     same = snr.double().cpu().numpy()
     assert [int(v) for v in got] == [O.count_peaks_bc(pl, 2.5, rule) for pl in same]
     assert sum(int(v) for v in got) > 0
+
+
+def test_bounded_noise_at_the_bench_configuration(ctx):
+    # the bench's bounded field: the 1000 x 1000 corner of the 1024^2 map,
+    # P = 2048, J = 7, mirror edges; R = 10 realisations run as two batches
+    # (9 + 1); every pixel of sigma against the oracle
+    ny = nx = 1000
+    P, J, R, seed, rule = 2048, 7, 10, 7, amap.BC_MIRROR
+    print("bounded noise at the bench configuration", flush=True)
+    _, g1, g2 = S.shear_map(1024, 11, 12)
+    g1, g2 = np.ascontiguousarray(g1[:ny, :nx]), np.ascontiguousarray(g2[:ny, :nx])
+    t1, t2 = dev(g1, torch.float32), dev(g2, torch.float32)
+    sigma, _ = ctx.noise_maps_bc(t1, t2, P, J, rule, R, seed)
+    torch.cuda.synchronize()
+    kE, _ = O.ks_invert_padded(g1, g2, P)
+    ref = O.noise_sigma_bc(g1, g2, P, J, rule, R, seed)
+    assert float(np.max(np.abs(sigma.double().cpu().numpy() - ref))) <= 1e-5 * rms(kE)
