@@ -1,6 +1,9 @@
 // Fields with edges and of any size: the starlet cascade under periodic,
-// mirror or zero boundary rules, and the zero extension and read-back
-// around the power-of-two KS inversion.
+// mirror or zero boundary rules (0, 1, 2), the zero extension and read-back
+// around the power-of-two KS inversion, the noise realisations' rotation
+// and running statistics (Sec. 1, Sec. 5.1: Welford's update in double,
+// then sigma and S/N), and peak counts with neighbours taken through the
+// edge rule (Sec. 2.2).
 //
 // The a trous cascade is that of Sec. 3 (B3 taps (1,4,6,4,1)/16 at dilation
 // 2^(j-1), row pass along x then column pass along y, w_j = c_{j-1} - c_j);
