@@ -39,7 +39,11 @@ if ROOT not in sys.path:
 
 METRIC = "Mpix·scales/s starlet+KS (% HBM peak), batched vs plain; p50/p99 latency served"
 HBM_PEAK_GBS = 8000.0
+# MI355X vector FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# = 78.6 TFLOP/s per instruction stream; 157.3 TFLOP/s counts packed
+# (two-wide) FP32 instructions, which this build does not emit
 FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
 
 N, J, R_REAL, SEED, THRESH = 1024, 7, 256, 23, 3.0
 TRAFFIC_PROFILE = "noise_path_1024_J7_R256_traffic.md"
@@ -63,6 +67,11 @@ def kernel_model(name, n, J, batch_real, stage_starts=()):
     signal's kernels (ks_cols_fwd, ks_rows, ks_cols_inv, starlet_stage_*)
     take one map; the noise kernels take the batch, two realisations per
     inverse transform (ks_rows_pair, ks_cols_inv_pair).
+
+    The bytes are the kernel's design hand-offs.  The bytes the *method*
+    requires are only the shear in and the planes, sigma and S/N out
+    (``compulsory_bytes``): a noise realisation needs no HBM traffic at all,
+    so every kernel of the noise loop is bounded by its arithmetic.
     """
     n2 = float(n * n)
     lg = n.bit_length() - 1
@@ -94,6 +103,53 @@ def kernel_model(name, n, J, batch_real, stage_starts=()):
     return models.get(name, (None, None))
 
 
+NOISE_KERNELS = ("ks_cols_fwd_rotate", "ks_rows_pair", "ks_cols_inv_pair", "merge_partials")
+
+
+def compulsory_bytes(name, n, J):
+    """HBM bytes the method itself requires of one launch: 0 for every
+    kernel of the noise loop (realisations live and die on the chip), the
+    input and output planes for the signal's kernels, sigma and S/N out
+    for the finalize step, the S/N planes in for the peak count."""
+    n2 = float(n * n)
+    if name in NOISE_KERNELS or name.startswith("noise_stage_j"):
+        return 0.0
+    return {"ks_cols_fwd": 8.0 * n2, "ks_rows": 0.0, "ks_cols_inv": 4.0 * n2,
+            "noise_finalize": 8.0 * (J - 1) * n2 + 4.0 * J * n2,
+            "count_peaks": 4.0 * (J - 1) * n2}.get(name, 4.0 * n2 if name.startswith("starlet_stage_j") else None)
+
+
+def roofline_of(name, n, J, B, starts, avg_s):
+    """The binding roofline of one kernel: HBM if its required bytes take
+    longer at 8 TB/s than its algorithmic flops at the FP32 peak, else ALU."""
+    b_des, f_alg = kernel_model(name, n, J, B, starts)
+    b_req = compulsory_bytes(name, n, J)
+    if f_alg is None or b_req is None:
+        return None
+    t_hbm = b_req / (HBM_PEAK_GBS * 1e9)
+    t_alu = f_alg / (FP32_PEAK_TFLOPS * 1e12)
+    if t_hbm >= t_alu:
+        ach = b_req / avg_s / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS}
+    ach = f_alg / avg_s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP32_PEAK_TFLOPS, "peak_nonpacked": FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": ach / FP32_NONPACKED_TFLOPS}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def kernel_sources_sha256():
     """Digest of the library's kernel sources (every source but the host-only
     api.hip); a stored counter summary is only used while it matches."""
@@ -107,12 +163,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+def measured_traffic(kernel, profile=TRAFFIC_PROFILE):
+    """HBM bytes per launch of ``kernel`` from a committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (each counter scaled by its reading for
     a copy of known size), or None when that summary was taken on other
     kernel sources or does not cover the kernel."""
-    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     sha, table = None, None
@@ -127,9 +183,23 @@ def measured_traffic(kernel):
     return table[kernel]["bytes_per_launch"]
 
 
+def _oracle_moments(args):
+    """One worker's run of realisations through the oracle (bench leg only)."""
+    import oracle
+    g1, g2, J_, seed, a, b = args
+    return oracle.noise_moments(g1, g2, J_, seed, a, b)
+
+
 def cpu_baseline(g1, g2, budget_s):
-    """Time the FP64 oracle on a bounded sample: the signal map plus as many
-    noise realisations as fit in about ``budget_s`` seconds."""
+    """Time the FP64 oracle on a bounded sample of the step: the signal map
+    plus as many noise realisations as fit in about ``budget_s`` seconds,
+    first on one core, then on all cores of the host (at most 16) with the
+    realisations spread over a process pool, each worker running the oracle
+    unchanged on a consecutive run of realisations and the runs merged by
+    the oracle's pairwise update."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
     import oracle
     t0 = time.perf_counter()
     kE, _ = oracle.ks_invert(g1, g2)
@@ -144,13 +214,35 @@ def cpu_baseline(g1, g2, budget_s):
     snr = oracle.snr_planes(planes, sig)
     oracle.count_peaks_planes(snr, THRESH)
     t_noise = time.perf_counter() - t2
-    units = 1 + r
-    total = t_sig + t_noise
-    return {"value": units * N * N * J / total / 1e6, "unit": "Mpix·scales/s",
-            "cores": 1, "kind": "oracle",
-            "sample": "the 1024x1024 map: KS + starlet (J=7) of the signal and %d noise "
-                      "realisations with sigma, S/N and peaks, %.1f s" % (r, total),
-            "cpu": platform.processor() or platform.machine()}
+    total1 = t_sig + t_noise
+    single = {"value": (1 + r) * N * N * J / total1 / 1e6, "cores": 1,
+              "sample": "the signal and %d noise realisations, %.1f s" % (r, total1)}
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores))
+    each = max(2, int(budget_s / max(per_real, 1e-3)))
+    r_all = cores * each
+    jobs = [(g1, g2, J, SEED, k * each, (k + 1) * each) for k in range(cores)]
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_moments, [(g1, g2, J, SEED, 0, 1)] * cores))  # start the workers
+        t3 = time.perf_counter()
+        acc = (0, 0.0, 0.0)
+        for part in ex.map(_oracle_moments, jobs):
+            acc = oracle.merge_moments(acc, part)
+        sig = oracle.sigma_from_moments(acc[0], acc[2])
+        snr = oracle.snr_planes(planes, sig)
+        oracle.count_peaks_planes(snr, THRESH)
+        t_all = time.perf_counter() - t3
+    total = t_sig + t_all
+    return {"value": (1 + r_all) * N * N * J / total / 1e6, "unit": "Mpix·scales/s",
+            "cores": cores, "kind": "oracle",
+            "sample": "the 1024x1024 map: KS + starlet (J=7) of the signal (one core, %.1f s) and "
+                      "%d noise realisations with sigma, S/N and peaks spread over %d worker "
+                      "processes (%d each, %.1f s)" % (t_sig, r_all, cores, each, t_all),
+            "cpu": cpu_model(), "single_core": single}
 
 
 def uneven_batch(ctx, reps):
@@ -406,21 +498,46 @@ def main():
 
     dom_avg_s = live[dom][1] / live[dom][0] * 1e-3
     b_alg, f_alg = kernel_model(dom, N, J, B, starts)
+    step_flops = 0.0
+    step_traffic = 0.0
+    traffic_complete = True
     for name, rec in kernels.items():
         bb, ff = kernel_model(name, N, J, B, starts)
         if bb is not None:
-            rec["alg_GBps"] = bb / (rec["avg_us"] * 1e-6) / 1e9
+            rec["design_GBps"] = bb / (rec["avg_us"] * 1e-6) / 1e9
             rec["alg_TFLOPs"] = ff / (rec["avg_us"] * 1e-6) / 1e12
+            step_flops += ff * rec["launches_per_step"]
+        rl = roofline_of(name, N, J, B, starts, rec["avg_us"] * 1e-6)
+        if rl:
+            rec["bound"] = rl["bound"]
+            rec["frac"] = rl["frac"]
+        tb = measured_traffic(name)
+        if tb is not None:
+            rec["hbm_meas_GBps"] = tb / (rec["avg_us"] * 1e-6) / 1e9
+            step_traffic += tb * rec["launches_per_step"]
+        else:
+            traffic_complete = False
     traffic = measured_traffic(dom)
-    roofline = {"kernel": dom, "bound": "hbm",
-                "achieved": b_alg / dom_avg_s / 1e9 if b_alg else None,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "traffic": traffic,
-                "bytes_per_launch": b_alg, "avg_launch_us": dom_avg_s * 1e6,
-                "launches_timed": live[dom][0],
-                "flops_per_launch": f_alg,
-                "tflops": f_alg / dom_avg_s / 1e12 if f_alg else None}
-    roofline["frac"] = roofline["achieved"] / roofline["peak"] if b_alg else None
+    roofline = {"kernel": dom}
+    roofline.update(roofline_of(dom, N, J, B, starts, dom_avg_s))
+    roofline.update({
+        "traffic": traffic,
+        "flops_per_launch": f_alg, "avg_launch_us": dom_avg_s * 1e6,
+        "launches_timed": live[dom][0],
+        # the kernel's own hand-offs (c planes, float64 accumulators) and the
+        # counters' HBM bytes beside them: the kernel is not bound by them,
+        # the ratio shows the re-reads of its tile halos
+        "design_bytes_per_launch": b_alg,
+        "hbm_meas_GBps": traffic / dom_avg_s / 1e9 if traffic else None,
+        "hbm_meas_frac": traffic / dom_avg_s / (HBM_PEAK_GBS * 1e9) if traffic else None,
+        "traffic_over_design_bytes": traffic / b_alg if (traffic and b_alg) else None,
+    })
+    step = {"alg_TFLOPs": step_flops / (ms_per_step * 1e-3) / 1e12,
+            "alg_flops": step_flops,
+            "frac_fp32": step_flops / (ms_per_step * 1e-3) / (FP32_PEAK_TFLOPS * 1e12),
+            "hbm_meas_bytes": step_traffic if traffic_complete else None,
+            "hbm_meas_frac": (step_traffic / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                              if traffic_complete else None)}
 
     # plain path: one map, KS + starlet, one launch sequence per map
     ke = out["kappa_e"]
@@ -556,6 +673,7 @@ def main():
         "direct_vs_starlet": direct,
         "bounded": bounded,
         "roofline": roofline,
+        "step": step,
         "kernels": kernels,
         # tile schedules the autotuner chose for this run: [j0, scales, tile
         # width, tile sub-rows, realisations per LDS pass] per stage

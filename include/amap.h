@@ -377,8 +377,18 @@ size_t amap_job_footprint_bytes(amap_dtype dt, int n, int J, int n_real);
 /* Realisations the noise statistics of an n x n map process per launch
  * sequence (the batch its kernels and workspace are sized for): about
  * 2^27 pixels of realisations, at least 1 and at most n_real.  0 if n is not
- * a supported side or n_real < 2. */
+ * a supported side or n_real < 2.  A context's amap_set_noise_batch cap
+ * lowers the batch its calls use. */
 int amap_noise_batch(int n, int n_real);
+
+/* Caps the noise realisations the context's calls process per launch
+ * sequence at max_batch (0 restores the default of amap_noise_batch).
+ * Results equal those of the default batch up to the rounding of how the
+ * per-batch statistics are merged (Chan's pairwise update, in double
+ * precision); the workspace stays sized for the default batch.  Smaller
+ * batches cost more merges; the cap exists so that the merge across
+ * batches can be exercised on small maps.  AMAP_E_INVAL if max_batch < 0. */
+amap_status amap_set_noise_batch(amap_ctx_t ctx, int max_batch);
 
 /* ---- serving: continuous batching of independent jobs ---- */
 
@@ -398,10 +408,15 @@ int amap_noise_batch(int n, int n_real);
 amap_status amap_server_create(amap_ctx_t ctx, amap_dtype dt, size_t mem_budget,
                                int max_inflight, int max_queued, amap_server_t* out);
 
-/* Validate and enqueue `job` (copied); `*ticket` identifies it.
- * AMAP_E_NOMEM if its footprint alone exceeds the budget (never
- * admissible); AMAP_E_BUSY if max_queued jobs already wait. */
-amap_status amap_server_submit(amap_server_t srv, const amap_job* job, long long* ticket);
+/* Validate and enqueue `job` (copied); `*ticket` identifies it.  An event
+ * is recorded on `stream` (a hipStream_t as void*, NULL = the null stream)
+ * at submission and the job's kernels wait for it, so the job runs after
+ * everything enqueued on `stream` before the call (for instance the work
+ * that produced its inputs or initialised its outputs), whatever slot it is
+ * admitted to.  AMAP_E_NOMEM if its footprint alone exceeds the budget
+ * (never admissible); AMAP_E_BUSY if max_queued jobs already wait. */
+amap_status amap_server_submit(amap_server_t srv, const amap_job* job, void* stream,
+                               long long* ticket);
 
 /* Admit what fits, then report whether `ticket` has finished (*done = 1;
  * its outputs are then complete and visible to later work on any stream).

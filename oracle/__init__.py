@@ -43,7 +43,8 @@ from .direct import map_direct, map_direct_at, map_kappa_form_radial  # noqa: F4
 from .rng import (  # noqa: F401
     philox4x64_10, phase_uniforms_u32, phase_uniforms, PHILOX_M0, PHILOX_M1,
 )
-from .noise import noise_sigma, snr_planes, rotate_shear  # noqa: F401
+from .noise import (noise_sigma, noise_moments, merge_moments, sigma_from_moments,  # noqa: F401
+                    snr_planes, rotate_shear)
 from .peaks import count_peaks, count_peaks_planes  # noqa: F401
 from .stats import (peak_histogram, peak_histogram_planes, plane_moments,  # noqa: F401
                     plane_moments_stack)

@@ -15,7 +15,8 @@ the signal.  Readings used here:
     as the signal; only the detail planes w_1 .. w_{J-1} are used;
   * sigma_j(x) is the unbiased sample standard deviation over the R
     realisations (divisor R - 1), per pixel and per scale, accumulated here
-    with Welford's update;
+    with Welford's update; statistics of disjoint runs of realisations
+    combine by the pairwise update of Chan, Golub & LeVeque (1979);
   * snr_j = w_j / sigma_j, and 0 where sigma_j = 0.
 
 Pins (tests/test_oracle_noise.py): the expected variance has a closed form by
@@ -23,6 +24,7 @@ linearity, E[sigma_j^2(x)] = 1/2 sum_y |K_j(x - y)|^2 |gamma(y)|^2 with K_j
 the complex impulse response of KS followed by scale j, checked on the mean
 over pixels within its chi-square scatter; degenerate angle streams
 (beta = 0 gives sigma = 0; beta alternating 0, pi gives sigma^2 = R/(R-1) w^2).
+The pairwise merge is pinned against numpy's variance of the pooled samples.
 """
 
 import numpy as np
@@ -39,6 +41,48 @@ def rotate_shear(g1, g2, u):
     return g1 * c - g2 * s, g1 * s + g2 * c
 
 
+def noise_moments(g1, g2, J, seed, r_begin, r_end, uniforms=None):
+    """Running statistics of the detail planes over realisations
+    r_begin .. r_end - 1: ``(count, mean, m2)``, with mean and m2 of shape
+    (J-1, N, N) and m2 the sum of squared deviations from the mean, built by
+    Welford's update one realisation at a time.
+
+    ``uniforms(n, seed, r)`` overrides the angle source (tests only).
+    """
+    g1 = np.asarray(g1, dtype=np.float64)
+    g2 = np.asarray(g2, dtype=np.float64)
+    n = g1.shape[0]
+    draw = phase_uniforms if uniforms is None else uniforms
+    mean = np.zeros((J - 1, n, n))
+    m2 = np.zeros((J - 1, n, n))
+    count = 0
+    for r in range(r_begin, r_end):
+        a1, a2 = rotate_shear(g1, g2, draw(n, seed, r))
+        kE, _ = ks_invert(a1, a2)
+        w = starlet_forward(kE, J)[:J - 1]
+        count += 1
+        delta = w - mean
+        mean += delta / count
+        m2 += delta * (w - mean)
+    return count, mean, m2
+
+
+def merge_moments(a, b):
+    """Statistics of the union of two disjoint sample sets from those of the
+    parts (the pairwise update of Chan, Golub & LeVeque, 1979):
+    n = na + nb, mean = ma + d nb / n, m2 = m2a + m2b + d^2 na nb / n with
+    d = mb - ma.  Each argument is ``(count, mean, m2)``."""
+    na, ma, qa = a
+    nb, mb, qb = b
+    if nb == 0:
+        return a
+    if na == 0:
+        return b
+    n = na + nb
+    d = mb - ma
+    return n, ma + d * (nb / n), qa + qb + d * d * (na * nb / n)
+
+
 def noise_sigma(g1, g2, J, n_real, seed, uniforms=None):
     """Per-pixel, per-scale noise sigma_j (shape (J-1, N, N)).
 
@@ -46,20 +90,15 @@ def noise_sigma(g1, g2, J, n_real, seed, uniforms=None):
     """
     if n_real < 2:
         raise ValueError("need at least two realisations")
-    g1 = np.asarray(g1, dtype=np.float64)
-    g2 = np.asarray(g2, dtype=np.float64)
-    n = g1.shape[0]
-    draw = phase_uniforms if uniforms is None else uniforms
-    mean = np.zeros((J - 1, n, n))
-    m2 = np.zeros((J - 1, n, n))
-    for r in range(n_real):
-        a1, a2 = rotate_shear(g1, g2, draw(n, seed, r))
-        kE, _ = ks_invert(a1, a2)
-        w = starlet_forward(kE, J)[:J - 1]
-        delta = w - mean
-        mean += delta / (r + 1)
-        m2 += delta * (w - mean)
-    return np.sqrt(m2 / (n_real - 1))
+    count, _, m2 = noise_moments(g1, g2, J, seed, 0, n_real, uniforms)
+    return sigma_from_moments(count, m2)
+
+
+def sigma_from_moments(count, m2):
+    """Unbiased sample standard deviation sqrt(m2 / (count - 1))."""
+    if count < 2:
+        raise ValueError("need at least two realisations")
+    return np.sqrt(m2 / (count - 1))
 
 
 def snr_planes(planes_signal, sigma):

@@ -95,7 +95,8 @@ def load():
         "amap_job_footprint_bytes": (ctypes.c_size_t, [I, I, I, I]),
         "amap_noise_batch": (I, [I, I]),
         "amap_server_create": (I, [P, I, ctypes.c_size_t, I, I, ctypes.POINTER(P)]),
-        "amap_server_submit": (I, [P, ctypes.POINTER(AmapJob), ctypes.POINTER(ctypes.c_longlong)]),
+        "amap_server_submit": (I, [P, ctypes.POINTER(AmapJob), P, ctypes.POINTER(ctypes.c_longlong)]),
+        "amap_set_noise_batch": (I, [P, I]),
         "amap_server_poll": (I, [P, ctypes.c_longlong, ctypes.POINTER(I)]),
         "amap_server_wait": (I, [P, ctypes.c_longlong]),
         "amap_server_completed": (I, [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]),
@@ -196,6 +197,10 @@ class Context:
         planner with sub-grid final noise stages where they apply."""
         mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
         _check(load().amap_set_autotune(self._h, mode))
+
+    def set_noise_batch(self, max_batch=0):
+        """Cap the noise realisations per launch sequence (0: the default)."""
+        _check(load().amap_set_noise_batch(self._h, int(max_batch)))
 
     def timing_enable(self, enable=True):
         _check(load().amap_timing_enable(self._h, 1 if enable else 0))
@@ -418,10 +423,12 @@ class Server:
         self._held = {}
 
     def submit(self, job):
+        """Queue a job; it runs after the work already enqueued on torch's
+        current stream.  Returns its ticket."""
         a = AmapJob()
         used = _fill_job(a, job)
         t = ctypes.c_longlong()
-        _check(load().amap_server_submit(self._h, ctypes.byref(a), ctypes.byref(t)))
+        _check(load().amap_server_submit(self._h, ctypes.byref(a), _stream(), ctypes.byref(t)))
         self._held[t.value] = used
         return t.value
 

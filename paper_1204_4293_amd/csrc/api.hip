@@ -169,6 +169,7 @@ struct amap_ctx {
     mutable std::map<std::array<int, 5>, StagePlan> plans;
     int autotune = 1;  // 0 analytic, 1 tuned, 2 analytic with sub-grid final noise stages
     mutable std::map<std::array<int, 5>, StagePlan> plans_sub;  // mode 2 schedules
+    int noise_cap = 0;  // > 0: at most this many noise realisations per launch sequence
 };
 
 namespace {
@@ -367,7 +368,10 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
                           T* sigma, T* snr, hipStream_t s) {
     const int logn = ilog2(n);
     const long long n2 = (long long)n * n;
-    const int B = noise_batch(n, n_real);
+    // the workspace is sized for the default batch; a context's cap only
+    // shrinks it
+    int B = noise_batch(n, n_real);
+    if (ctx->noise_cap > 0 && ctx->noise_cap < B) B = ctx->noise_cap;
     const size_t plane_b = align256((size_t)B * n2 * sizeof(T));
     char* p = ws;
     cpx<T>* C = reinterpret_cast<cpx<T>*>(p);   p += align256((size_t)B * n2 * 2 * sizeof(T));
@@ -582,6 +586,14 @@ amap_status amap_set_autotune(amap_ctx_t c, int enable) {
     if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
     if (enable < 0 || enable > 2) return fail(AMAP_E_INVAL, "autotune mode must be 0, 1 or 2");
     c->autotune = enable;
+    return AMAP_OK;
+}
+
+amap_status amap_set_noise_batch(amap_ctx_t c, int max_batch) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    if (max_batch < 0) return fail(AMAP_E_INVAL, "max_batch must be >= 0 (got %d)", max_batch);
+    c->noise_cap = max_batch;
     return AMAP_OK;
 }
 
@@ -1437,6 +1449,7 @@ struct amap_server {
         long long ticket;
         amap_job job;
         size_t footprint;
+        hipEvent_t ready;         // recorded on the submitting stream at submit
     };
     amap_ctx* ctx = nullptr;
     amap_dtype dt = AMAP_F32;
@@ -1449,6 +1462,19 @@ struct amap_server {
     std::vector<long long> finished;          // done, not yet reported by amap_server_completed
     char* arena = nullptr;                    // mem_budget bytes of device memory, allocated once
     std::map<size_t, size_t> holes;           // free ranges of the arena: offset -> length
+    std::vector<hipEvent_t> events;           // reusable submit events
+
+    hipEvent_t get_event() {
+        hipEvent_t e = nullptr;
+        if (!events.empty()) {
+            e = events.back();
+            events.pop_back();
+        } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+        }
+        return e;
+    }
 
     // First fit of `bytes` (a multiple of 256) in the arena; false if no hole fits.
     bool take(size_t bytes, size_t* off) {
@@ -1486,6 +1512,8 @@ amap_status launch_on_slot(amap_server* v, amap_server::Slot& sl, const amap_ser
                            size_t off) {
     TimerScope ts(v->ctx);
     char* w = v->arena + off;
+    // the job runs after the work its submitter enqueued before submitting
+    AMAP_HIP(hipStreamWaitEvent(sl.stream, p.ready, 0), "wait for the submitting stream");
     AMAP_TRY(v->dt == AMAP_F32 ? enqueue_job<float>(v->ctx, w, p.job, sl.stream)
                                : enqueue_job<double>(v->ctx, w, p.job, sl.stream));
     AMAP_HIP(hipEventRecord(sl.done, sl.stream), "done event");
@@ -1526,6 +1554,8 @@ amap_status pump(amap_server* v) {
             v->give(off, p.footprint);
             return st;
         }
+        // the slot's wait has taken the event's state; it can be recorded again
+        v->events.push_back(p.ready);
         v->queue.erase(v->queue.begin());
     }
     return AMAP_OK;
@@ -1578,7 +1608,8 @@ amap_status amap_server_create(amap_ctx_t c, amap_dtype dt, size_t mem_budget, i
     return AMAP_OK;
 }
 
-amap_status amap_server_submit(amap_server_t v, const amap_job* job, long long* ticket) {
+amap_status amap_server_submit(amap_server_t v, const amap_job* job, void* stream,
+                               long long* ticket) {
     g_last_error.clear();
     if (!v) return fail(AMAP_E_INVAL, "server must not be NULL");
     if (!job || !ticket) return fail(AMAP_E_INVAL, "job and ticket must not be NULL");
@@ -1593,8 +1624,15 @@ amap_status amap_server_submit(amap_server_t v, const amap_job* job, long long* 
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", v->ctx->device);
     AMAP_TRY(pump(v));
     if ((int)v->queue.size() >= v->max_queued) return fail(AMAP_E_BUSY, "queue full");
+    hipEvent_t ev = v->get_event();
+    if (!ev) return fail(AMAP_E_HIP, "cannot create a submit event");
+    const hipError_t er = hipEventRecord(ev, static_cast<hipStream_t>(stream));
+    if (er != hipSuccess) {
+        v->events.push_back(ev);
+        return hip_fail(er, "record the submit event");
+    }
     const long long t = v->next_ticket++;
-    v->queue.push_back(amap_server::Pending{t, *job, fp});
+    v->queue.push_back(amap_server::Pending{t, *job, fp, ev});
     v->state[t] = 0;
     *ticket = t;
     return pump(v);
@@ -1673,6 +1711,9 @@ amap_status amap_server_destroy(amap_server_t v) {
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    for (const amap_server::Pending& p : v->queue)  // left behind only after an error
+        if (p.ready) (void)hipEventDestroy(p.ready);
+    for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     if (v->arena) (void)hipFree(v->arena);
     delete v;
     return st;

@@ -72,6 +72,33 @@ def test_results_same_alone_and_in_the_mix(ctx):
                 j["g1"].shape[0], key)
 
 
+def test_job_waits_for_its_submitting_stream(ctx):
+    # the inputs are written on a side stream behind a long queue of work and
+    # the job is submitted on that stream: it must see the written inputs,
+    # not the zeros they held before
+    job = make_job(256, 700, 8)
+    src1, src2 = job["g1"].clone(), job["g2"].clone()
+    job["g1"].zero_()
+    job["g2"].zero_()
+    a = torch.randn(2048, 2048, device="cuda")
+    torch.cuda.synchronize()
+    srv = amap.Server(ctx, mem_budget=1 << 30, max_inflight=2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for _ in range(40):
+            a = torch.tanh(a @ a)  # keeps the stream busy for a while
+        job["g1"].copy_(src1)
+        job["g2"].copy_(src2)
+        t = srv.submit(job)
+    srv.wait(t)
+    srv.close()
+    torch.cuda.synchronize()
+    ref = run_alone(ctx, job)
+    torch.cuda.synchronize()
+    for key in ("planes", "sigma", "snr", "peaks"):
+        assert torch.equal(job[key], ref[key]), key
+
+
 def test_admission_respects_the_budget(ctx):
     jobs = [make_job(256, 400 + i, 8) for i in range(4)]
     fp = amap.job_footprint_bytes(amap.F32, 256, jobs[0]["planes"].shape[0], 8)

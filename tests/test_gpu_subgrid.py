@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import oracle as O
+import oracle_pool
 import synth as S
 import paper_1204_4293_amd as amap
 
@@ -62,10 +63,9 @@ def test_subgrid_stage_against_oracle_and_tiles(ctxs, n, J, R, dtype, j0):
     a, b = sa.double().cpu().numpy(), sb.double().cpu().numpy()
     scale = float(np.abs(b).max())
     assert float(np.abs(a - b).max()) <= (1e-6 if dtype == torch.float32 else 1e-12) * scale
-    if n <= 1024:
-        kE, _ = O.ks_invert(g1, g2)
-        ref = O.noise_sigma(g1, g2, J, R, seed)
-        assert float(np.abs(a - ref).max()) <= TOL[dtype] * rms(kE)
+    kE, _ = O.ks_invert(g1, g2)
+    ref = oracle_pool.noise_sigma_pool(g1, g2, J, R, seed)
+    assert float(np.abs(a - ref).max()) <= TOL[dtype] * rms(kE)
 
 
 def test_subgrid_path_snr_and_peaks_match_oracle(ctxs):

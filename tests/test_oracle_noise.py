@@ -62,3 +62,47 @@ def test_rotation_is_a_phase():
     a1, a2 = O.rotate_shear(g1, g2, u)
     z = (g1 + 1j * g2) * np.exp(2j * np.pi * u)
     assert np.max(np.abs(a1 - z.real)) < 1e-15 and np.max(np.abs(a2 - z.imag)) < 1e-15
+
+
+def test_merge_moments_matches_pooled_variance():
+    # Chan-Golub-LeVeque pairwise update vs numpy's mean and variance of the
+    # pooled samples; unequal parts with far-apart means exercise the
+    # between-part term d^2 na nb / n
+    rng = np.random.default_rng(5)
+    parts = [rng.standard_normal((k, 3, 4)) * s + m
+             for k, s, m in ((3, 1.0, 0.0), (1, 0.5, 40.0), (7, 2.0, -3.0), (2, 0.1, 9.0))]
+    acc = (0, 0.0, 0.0)
+    for p in parts:
+        acc = O.merge_moments(acc, (p.shape[0], p.mean(axis=0), ((p - p.mean(axis=0)) ** 2).sum(axis=0)))
+    pooled = np.concatenate(parts)
+    assert acc[0] == pooled.shape[0]
+    assert np.allclose(acc[1], pooled.mean(axis=0), rtol=0, atol=1e-13 * np.abs(pooled).max())
+    ref = np.var(pooled, axis=0) * pooled.shape[0]
+    assert np.allclose(acc[2], ref, rtol=1e-12, atol=0)
+    # merging with an empty part is the identity
+    assert O.merge_moments(acc, (0, 0.0, 0.0)) is acc
+
+
+def test_noise_moments_split_runs_merge_to_the_single_run():
+    _, g1, g2 = S.shear_map(32, 7, 8)
+    J, R, seed = 4, 9, 31
+    whole = O.noise_moments(g1, g2, J, seed, 0, R)
+    acc = (0, 0.0, 0.0)
+    for a, b in ((0, 2), (2, 3), (3, 9)):
+        acc = O.merge_moments(acc, O.noise_moments(g1, g2, J, seed, a, b))
+    assert acc[0] == whole[0] == R
+    scale = np.abs(whole[1]).max()
+    assert np.max(np.abs(acc[1] - whole[1])) <= 1e-14 * scale
+    assert np.max(np.abs(acc[2] - whole[2])) <= 1e-13 * np.abs(whole[2]).max()
+    sig = O.noise_sigma(g1, g2, J, R, seed)
+    assert np.array_equal(O.sigma_from_moments(*whole[::2]), sig)
+
+
+def test_pooled_oracle_helper_equals_noise_sigma():
+    # the process-pool helper the large GPU parity tests use
+    import oracle_pool
+    _, g1, g2 = S.shear_map(32, 9, 10)
+    J, R, seed = 4, 7, 12
+    ref = O.noise_sigma(g1, g2, J, R, seed)
+    got = oracle_pool.noise_sigma_pool(g1, g2, J, R, seed, workers=3)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(ref)
