@@ -165,6 +165,24 @@ amap_status amap_ks_invert(amap_ctx_t ctx, amap_dtype dt, int n,
                            void* kappa_e, void* kappa_b, void* stream);
 
 /*
+ * amap_ks_invert without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, arguments, layout and results as
+ * amap_ks_invert, but the complex spectrum lives in a static scratch array
+ * of 64 MiB that each GPU holds from the first amap_create on it until the
+ * process ends, instead of the context's workspace.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  Limit:
+ * 2 n^2 elements of scratch, i.e. n <= 2048 for float32 and float64;
+ * larger n returns AMAP_E_INVAL.  Every such call on one GPU shares that
+ * GPU's array (all contexts), which keeps the last call's contents: calls
+ * that overlap in time on one GPU (on different streams or host threads)
+ * race and must be ordered by the caller.
+ */
+amap_status amap_ks_invert_noalloc(amap_ctx_t ctx, amap_dtype dt, int n,
+                                   const void* g1, const void* g2,
+                                   void* kappa_e, void* kappa_b, void* stream);
+
+/*
  * Starlet decomposition (Sec. 3; eq:splinewl with the B3 spline of
  * Sec. 4.2): planes[J][n][n] = w_1 .. w_{J-1}, c_{J-1}, with c_0 = kappa,
  * c_j = column(row(c_{j-1})) at dilation 2^(j-1), w_j = c_{j-1} - c_j.

@@ -76,6 +76,7 @@ def load():
         "amap_timing_read": (I, [P, ctypes.c_char_p, ctypes.c_size_t, I]),
         "amap_timing_select": (I, [P, ctypes.c_char_p]),
         "amap_ks_invert": (I, [P, I, I, P, P, P, P, P]),
+        "amap_ks_invert_noalloc": (I, [P, I, I, P, P, P, P, P]),
         "amap_starlet_forward": (I, [P, I, I, I, P, P, P]),
         "amap_starlet_forward_bc": (I, [P, I, I, I, I, I, P, P, P]),
         "amap_ks_invert_padded": (I, [P, I, I, I, I, P, P, P, P, P]),
@@ -229,6 +230,14 @@ class Context:
             kappa_b = self._empty((n, n), g1)
         _check(load().amap_ks_invert(self._h, _dt(g1), n, _ptr(g1), _ptr(g2), _ptr(kappa_e),
                                      _ptr(kappa_b), _stream()))
+        return kappa_e, kappa_b
+
+    def ks_invert_noalloc(self, g1, g2, kappa_e, kappa_b=None):
+        """ks_invert through the entry point that allocates nothing (its
+        spectrum in the library's static scratch); outputs must be given."""
+        n = _side(g1)
+        _check(load().amap_ks_invert_noalloc(self._h, _dt(g1), n, _ptr(g1), _ptr(g2), _ptr(kappa_e),
+                                             _ptr(kappa_b), _stream()))
         return kappa_e, kappa_b
 
     def starlet_forward(self, kappa, J, planes=None):

@@ -409,6 +409,45 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
 
 }  // namespace amap
 
+// ---- static scratch of the no-allocation entry point ---------------------------------
+// amap_ks_invert_noalloc takes its complex spectrum from this file-scope
+// device array instead of the context's workspace.  Each GPU the library
+// runs on holds its own copy until the process ends; host code reaches it
+// only through the device address hipGetSymbolAddress returns (the array's
+// name is a host-side stand-in, not a device address), looked up once per
+// device when a context is created there.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;    // device -> address of its copy
+std::map<int, std::string> g_scratch_err;
+
+// With `device` current: look up and keep the device's scratch address.
+void scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        g_scratch_err[device] = hipGetErrorString(e);
+        return;
+    }
+    g_scratch_ptr[device] = ptr;
+}
+
+void* scratch_of(int device, std::string* why) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    auto er = g_scratch_err.find(device);
+    *why = er != g_scratch_err.end() ? er->second : "not set up on this device";
+    return nullptr;
+}
+}  // namespace
+
 // ---- C ABI -------------------------------------------------------------------------------
 extern "C" {
 
@@ -428,6 +467,7 @@ amap_status amap_create(int hip_device, amap_ctx_t* out) {
     amap_ctx* c = new (std::nothrow) amap_ctx;
     if (!c) return fail(AMAP_E_NOMEM, "out of host memory");
     c->device = hip_device;
+    scratch_setup(hip_device);  // the no-allocation entry point's scratch on this device
     amap_status s = upload_twiddles<float>(&c->tw32);
     if (s == AMAP_OK) s = upload_twiddles<double>(&c->tw64);
     if (s != AMAP_OK) {
@@ -661,6 +701,42 @@ amap_status amap_ks_invert(amap_ctx_t c, amap_dtype dt, int n, const void* g1, c
                                  (long long)n * n, false, 0, 0, s);
     return enqueue_ks<double>(c, logn, 1, (const double*)g1, (const double*)g2, 0,
                               (cpx<double>*)c->ws.ptr, (double*)kappa_e, (double*)kappa_b,
+                              (long long)n * n, false, 0, 0, s);
+}
+
+amap_status amap_ks_invert_noalloc(amap_ctx_t c, amap_dtype dt, int n, const void* g1,
+                                   const void* g2, void* kappa_e, void* kappa_b, void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    AMAP_TRY(check_n(n));
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(kappa_e, "kappa_e"));
+    AMAP_TRY(check_ptr(kappa_b, "kappa_b", false));
+    const size_t bytes = (size_t)n * n * esize(dt);
+    if (overlaps(kappa_e, bytes, g1, bytes) || overlaps(kappa_e, bytes, g2, bytes) ||
+        overlaps(kappa_b, bytes, g1, bytes) || overlaps(kappa_b, bytes, g2, bytes) ||
+        overlaps(kappa_e, bytes, kappa_b, bytes))
+        return fail(AMAP_E_INVAL, "outputs may not overlap inputs or each other");
+    if (2 * bytes > kNoAllocScratchBytes)
+        return fail(AMAP_E_INVAL,
+                    "n = %d needs %zu bytes of scratch; the no-allocation entry point holds %zu "
+                    "(float32 and float64 up to n = 2048)", n, 2 * bytes, kNoAllocScratchBytes);
+    std::string why;
+    void* sp = scratch_of(c->device, &why);
+    if (!sp) return fail(AMAP_E_HIP, "static scratch of device %d unavailable: %s", c->device, why.c_str());
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int logn = ilog2(n);
+    if (dt == AMAP_F32)
+        return enqueue_ks<float>(c, logn, 1, (const float*)g1, (const float*)g2, 0,
+                                 static_cast<cpx<float>*>(sp), (float*)kappa_e, (float*)kappa_b,
+                                 (long long)n * n, false, 0, 0, s);
+    return enqueue_ks<double>(c, logn, 1, (const double*)g1, (const double*)g2, 0,
+                              static_cast<cpx<double>*>(sp), (double*)kappa_e, (double*)kappa_b,
                               (long long)n * n, false, 0, 0, s);
 }
 
