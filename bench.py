@@ -54,24 +54,34 @@ GRF_SEED, NOISE_SEED = 11, 12
 
 
 def kernel_model(name, n, J, batch_real, stage_starts=()):
-    """Algorithmic bytes and flops of one launch of each kernel (float32).
+    """Design bytes and algorithmic flops of one launch of each kernel (float32).
 
-    bytes: the kernel's compulsory input + output, each operand read or
-    written once per launch (the shared shear map once per launch; the
-    double-precision noise accumulators read and written once per launch);
-    flops: 5 m log2 m per length-m complex FFT, 6 per complex multiply,
-    19 per pixel and starlet scale (two 5-tap B3 filters and a difference),
-    4 per pixel and scale for the running mean and squared deviation.
-    ``stage_starts`` lists the first scale of each noise stage (from the
-    kernel names), which fixes how many scales a stage covers.  The
-    signal's kernels (ks_cols_fwd, ks_rows, ks_cols_inv, starlet_stage_*)
-    take one map; the noise kernels take the batch, two realisations per
-    inverse transform (ks_rows_pair, ks_cols_inv_pair).
+    flops follow the per-realisation work of the method: 5 m log2 m per
+    length-m complex FFT, so 20 n^2 log2 n for the forward and inverse 2-D
+    transforms of one map; 6 per complex multiply (the KS kernel); 50 per
+    pixel for the random phase and the rotation; 19 per pixel and starlet
+    scale (two 5-tap B3 filters and a difference); 4 per pixel and scale for
+    the running mean and squared deviation.  Each kernel is credited with
+    the part of that work it carries out: the column pass the forward
+    column FFTs (and the phases), the row pass the forward and inverse row
+    FFTs and the multiply, the inverse column pass the inverse column FFTs.
+    The paired kernels (ks_rows_pair, ks_cols_inv_pair) finish two
+    realisations' inverse transforms in one (their kappa_E are the real and
+    imaginary parts of one transform), so they complete the credited work
+    with half of the inverse arithmetic.
 
-    The bytes are the kernel's design hand-offs.  The bytes the *method*
-    requires are only the shear in and the planes, sigma and S/N out
-    (``compulsory_bytes``): a noise realisation needs no HBM traffic at all,
-    so every kernel of the noise loop is bounded by its arithmetic.
+    bytes: the kernel's design hand-offs, each operand read or written once
+    per launch (the shared shear map once per launch; the double-precision
+    noise accumulators read and written once per launch).  ``stage_starts``
+    lists the first scale of each noise stage (from the kernel names), which
+    fixes how many scales a stage covers.  The signal's kernels
+    (ks_cols_fwd, ks_rows, ks_cols_inv, starlet_stage_*) take one map; the
+    noise kernels take the batch.
+
+    The bytes the *method* requires are only the shear in and the planes,
+    sigma and S/N out (``compulsory_bytes``): a noise realisation needs no
+    HBM traffic at all, so every kernel of the noise loop is bounded by its
+    arithmetic.
     """
     n2 = float(n * n)
     lg = n.bit_length() - 1
@@ -79,14 +89,14 @@ def kernel_model(name, n, J, batch_real, stage_starts=()):
     P = (B + 1) // 2  # realisation pairs
     fft1d = 5.0 * n2 * lg  # n transforms of length n
     models = {
-        "ks_cols_fwd_rotate": (8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 6.0 * n2)),
+        "ks_cols_fwd_rotate": (8.0 * n2 + 8.0 * n2 * B, B * (fft1d + 50.0 * n2)),
         "ks_cols_fwd": (16.0 * n2, fft1d),
         "ks_rows": (16.0 * n2, 2 * fft1d + 6.0 * n2),
         "ks_cols_inv": (12.0 * n2, fft1d),
-        # read B spectra, write P packed ones; B forward, P inverse transforms
-        "ks_rows_pair": (8.0 * n2 * (B + P), B * (fft1d + 6.0 * n2) + P * fft1d),
+        # read B spectra, write P packed ones
+        "ks_rows_pair": (8.0 * n2 * (B + P), B * (2 * fft1d + 6.0 * n2)),
         # read P packed spectra, write B real maps
-        "ks_cols_inv_pair": (8.0 * n2 * P + 4.0 * n2 * B, P * fft1d),
+        "ks_cols_inv_pair": (8.0 * n2 * P + 4.0 * n2 * B, B * fft1d),
         "noise_finalize": ((16.0 + 12.0) * (J - 1) * n2, 3.0 * (J - 1) * n2),
         "count_peaks": (4.0 * (J - 1) * n2, 9.0 * (J - 1) * n2),
     }
@@ -245,12 +255,42 @@ def cpu_baseline(g1, g2, budget_s):
             "cpu": cpu_model(), "single_core": single}
 
 
+def _gen_map(args):
+    """One synthetic shear map (bench set-up, worker process)."""
+    import numpy as np
+
+    import synth
+    n, grf_seed, noise_seed = args
+    _, g1, g2 = synth.shear_map(n, grf_seed, noise_seed)
+    return np.asarray(g1, dtype=np.float32), np.asarray(g2, dtype=np.float32)
+
+
+def generate_maps(specs):
+    """synth.shear_map for each (n, grf_seed, noise_seed), spread over up to
+    16 worker processes; float32 arrays in the order given."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores, len(specs)))
+    # largest first, so the pool ends together
+    order = sorted(range(len(specs)), key=lambda i: -specs[i][0])
+    out = [None] * len(specs)
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        for i, res in zip(order, ex.map(_gen_map, [specs[i] for i in order], chunksize=4)):
+            out[i] = res
+    return out
+
+
 def uneven_batch(ctx, reps):
     """The uneven batch: 512 float32 maps, sides drawn from {128..2048}
     (weights 4:4:3:2:1, seed 31), J = log2 N - 2, KS + starlet per map, as
     one grouped graph-captured plan and as one launch sequence per map.
-    Inputs come from a pool of two generated maps per side (job i uses pool
-    entry i % 2); every job has its own output planes."""
+    Every map is its own synthetic field (seeds 1000 + i and 5000 + i), so
+    the 2.2 GB of inputs come from HBM, not from the 256 MB last-level
+    cache; every job has its own output planes."""
     import torch
 
     import synth
@@ -258,23 +298,18 @@ def uneven_batch(ctx, reps):
 
     dev = torch.device("cuda", 0)
     sides = synth.uneven_batch_sides(512, 31)
-    pool = {}
-    for n in sorted(set(sides)):
-        pool[n] = []
-        for k in range(2):
-            _, g1, g2 = synth.shear_map(n, 1000 + 2 * n + k, 5000 + 2 * n + k)
-            pool[n].append((torch.tensor(g1, dtype=torch.float32, device=dev),
-                            torch.tensor(g2, dtype=torch.float32, device=dev)))
+    maps = generate_maps([(n, 1000 + i, 5000 + i) for i, n in enumerate(sides)])
     jobs = []
     units = 0.0
     b_alg = 0.0
     for i, n in enumerate(sides):
         J = n.bit_length() - 1 - 2
-        g1, g2 = pool[n][i % 2]
-        jobs.append({"g1": g1, "g2": g2,
+        g1, g2 = maps[i]
+        jobs.append({"g1": torch.from_numpy(g1).to(dev), "g2": torch.from_numpy(g2).to(dev),
                      "planes": torch.empty((J, n, n), dtype=torch.float32, device=dev)})
         units += n * n * J
         b_alg += n * n * (8.0 + 4.0 * J)
+    del maps
     plan = amap.BatchPlan(ctx, jobs)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
@@ -305,7 +340,8 @@ def uneven_batch(ctx, reps):
     t_plain = e0.elapsed_time(e1) / max(1, reps // 2) * 1e-3
     plan.close()
     counts = {str(n): sides.count(n) for n in sorted(set(sides))}
-    return {"workload": "512 float32 maps, sides %s, J = log2 N - 2, KS + starlet" % counts,
+    return {"workload": "512 distinct float32 maps (seeds 1000+i), sides %s, J = log2 N - 2, "
+                        "KS + starlet" % counts,
             "value": units / t_batched / 1e6, "unit": "Mpix·scales/s", "ms_per_batch": t_batched * 1e3,
             "hbm_alg_GBps": b_alg / t_batched / 1e9,
             "hbm_alg_frac": b_alg / t_batched / (HBM_PEAK_GBS * 1e9),
@@ -314,15 +350,16 @@ def uneven_batch(ctx, reps):
                       "hbm_alg_frac": b_alg / t_plain / (HBM_PEAK_GBS * 1e9)}}
 
 
-def served_stream(ctx, level_seconds):
+def served_stream(ctx, requests):
     """The served stream: Poisson arrivals of float32 maps with sides
     log-uniform over 256..4096 (seeds 41, 42), J = min(9, log2 N - 2), 32 noise
-    realisations each, through the library's request loop (footprint
-    admission, 8 concurrent slots).  Inputs come from a device-resident pool
-    of two maps per side; outputs come from a fixed set of buffers per side
-    (requests wait for one on the client side, inside their latency).  First a burst
-    gives the saturated request rate mu, then the stream runs at 0.5 mu and
-    0.8 mu; latency is arrival -> completion seen by polling."""
+    realisations each (noise seed 6000 + id), through the library's request
+    loop (footprint admission, 8 concurrent slots).  Inputs come from a
+    device-resident pool of eight generated maps per side; outputs come from
+    a fixed set of buffers per side (requests wait for one on the client
+    side, inside their latency).  First a burst gives the saturated request
+    rate mu, then the stream runs ``requests`` requests at each of 0.25,
+    0.5 and 0.8 mu; latency is arrival -> completion seen by polling."""
     import numpy as np
     import torch
 
@@ -331,13 +368,13 @@ def served_stream(ctx, level_seconds):
 
     dev = torch.device("cuda", 0)
     R = 32
-    pool = {}
-    for n in (256, 512, 1024, 2048, 4096):
-        pool[n] = []
-        for k in range(2):
-            _, g1, g2 = synth.shear_map(n, 7000 + 2 * n + k, 9000 + 2 * n + k)
-            pool[n].append((torch.tensor(g1, dtype=torch.float32, device=dev),
-                            torch.tensor(g2, dtype=torch.float32, device=dev)))
+    sizes = (256, 512, 1024, 2048, 4096)
+    specs = [(n, 7000 + 8 * n + k, 9000 + 8 * n + k) for n in sizes for k in range(8)]
+    maps = generate_maps(specs)
+    pool = {n: [] for n in sizes}
+    for (n, _, _), (g1, g2) in zip(specs, maps):
+        pool[n].append((torch.from_numpy(g1).to(dev), torch.from_numpy(g2).to(dev)))
+    del maps
     srv = amap.Server(ctx, torch.float32, mem_budget=48 << 30, max_inflight=8, max_queued=100000)
     # output buffers: a fixed set per side, reused; a request waits on the
     # client side (inside its latency) until a set of its side is free
@@ -364,7 +401,7 @@ def served_stream(ctx, level_seconds):
                 n = sides[k]
                 J = min(9, n.bit_length() - 1 - 2)
                 outs = free[n].pop()
-                g1, g2 = pool[n][k % 2]
+                g1, g2 = pool[n][k % 8]
                 job = dict(outs, g1=g1, g2=g2, n_real=R, seed=6000 + k, threshold=3.0)
                 pending[srv.submit(job)] = (t0 + times[k], (1 + R) * n * n * J, n, outs)
             fin = srv.completed()
@@ -377,23 +414,23 @@ def served_stream(ctx, level_seconds):
                 units += u
         span = done_at - t0
         lat = np.array(lat) * 1e3
-        return {"requests": len(times), "p50_ms": float(np.percentile(lat, 50)),
+        return {"requests": len(times), "seconds": span, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "maps_per_s": len(times) / span,
                 "value": units / span / 1e6, "unit": "Mpix·scales/s"}
 
     # warm up every size once, then the saturated burst
-    run(np.zeros(5), [256, 512, 1024, 2048, 4096])
-    _, sides = synth.served_stream(48, 1.0)
-    burst = run(np.zeros(48), sides)
+    run(np.zeros(5), list(sizes))
+    _, sides = synth.served_stream(96, 1.0)
+    burst = run(np.zeros(96), sides)
     mu = burst["maps_per_s"]
     out = {"workload": "Poisson arrivals, float32 sides log-uniform 256..4096, J = min(9, log2 N - 2), "
-                       "R = 32 per request, 8 slots, footprint admission",
+                       "R = 32 per request, 8 slots, footprint admission, 8 input maps per side",
            "saturated": burst, "levels": {}}
-    for frac in (0.5, 0.8):
+    for frac in (0.25, 0.5, 0.8):
         qps = frac * mu
-        count = int(min(400, max(30, qps * level_seconds)))
-        times, sides = synth.served_stream(count, qps)
-        out["levels"]["%.1f_mu" % frac] = dict(run(times, sides), qps=qps)
+        times, sides = synth.served_stream(requests, qps)
+        out["levels"]["%.2f_mu" % frac] = dict(run(times, sides), qps=qps)
+        print("bench: served %.2f mu done" % frac, file=sys.stderr, flush=True)
     srv.close()
     return out
 
@@ -407,8 +444,8 @@ def main():
                     help="budget of the oracle's timed sample (0 to skip)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-batch and served-stream measurements (profiler runs)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
-                    help="length of each served-stream level")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests at each load level of the served stream (0 skips the stream)")
     ap.add_argument("--schedules", default=os.path.join(ROOT, "profiles", SCHEDULES),
                     help="JSON of tile schedules to load (amap_plans_load) instead of tuning; "
                          "'none' tunes live")
@@ -651,8 +688,9 @@ def main():
     if not args.no_batched:
         print("bench: uneven batch", file=sys.stderr, flush=True)
         batched = uneven_batch(ctx, max(2, args.steps))
-        print("bench: served stream", file=sys.stderr, flush=True)
-        served = served_stream(ctx, args.serve_seconds)
+        if args.serve_requests > 0:
+            print("bench: served stream", file=sys.stderr, flush=True)
+            served = served_stream(ctx, args.serve_requests)
 
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix·scales/s", "n_gpus": 1,

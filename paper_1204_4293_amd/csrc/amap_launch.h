@@ -146,9 +146,15 @@ hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, 
 // Direct aperture mass: taps for offsets dy in [-R, R] (row dy + R), the
 // dx range [-half[dy+R], half[dy+R]] (half < 0: empty row), weights wc
 // (Q cos 2phi) and ws (Q sin 2phi) dense [(2R+1)][(2R+1)] in T.
+// gtab (may be null): the weights regrouped for the LDS row kernel (maps
+// from 512 px wide): row dy + R holds, per group of four dx from
+// dx = -R4 (R4 = R rounded up to a multiple of 4), four Q cos 2phi then four
+// Q sin 2phi, R4 / 2 + 1 groups, zero outside the disc;
+// map_direct_uses_groups tells whether the row kernel runs (and needs it).
 template <typename T>
 hipError_t launch_map_direct(int logn, const T* g1, const T* g2, int R, const int* half,
-                             const T* wc, const T* ws, T* out, hipStream_t s);
+                             const T* wc, const T* ws, const T* gtab, T* out, hipStream_t s);
+bool map_direct_uses_groups(int logn, int R, size_t elem);
 
 // Starlet of `maps` ny x nx fields (any sizes >= 2) under a boundary rule
 // (0 periodic, 1 mirror: whole-sample symmetric, 2 zero outside): J planes

@@ -991,6 +991,57 @@ amap_status amap_starlet_reconstruct(amap_ctx_t c, amap_dtype dt, int n, int J,
     return AMAP_OK;
 }
 
+}  // extern "C"
+
+// Uploads the direct sum's tap tables into the context's workspace and
+// launches it: the row offsets' dx ranges, the dense weights and, for the
+// LDS row kernel, the weights regrouped by four dx (zero outside the disc).
+template <typename T>
+static amap_status enqueue_direct(amap_ctx* c, const TapTable& tab, int logn, const T* g1,
+                                  const T* g2, T* out, hipStream_t s) {
+    const int R = tab.R, D = 2 * R + 1;
+    const int R4 = (R + 3) / 4 * 4, ng = R4 / 2 + 1;
+    const bool grouped = map_direct_uses_groups(logn, R, sizeof(T));
+    const size_t off_w = align256((size_t)D * sizeof(int));
+    const size_t wbytes = align256((size_t)D * D * sizeof(T));
+    const size_t gbytes = grouped ? align256((size_t)D * ng * 8 * sizeof(T)) : 0;
+    AMAP_TRY(c->ws.reserve(off_w + 2 * wbytes + gbytes));
+    char* base = static_cast<char*>(c->ws.ptr);
+    std::vector<T> wc(tab.wc.begin(), tab.wc.end()), ws(tab.ws.begin(), tab.ws.end());
+    std::vector<T> gt;
+    if (grouped) {
+        gt.assign((size_t)D * ng * 8, (T)0);
+        for (int dy = -R; dy <= R; ++dy)
+            for (int k = 0; k < ng; ++k)
+                for (int q = 0; q < 4; ++q) {
+                    const int dx = 4 * k - R4 + q;
+                    if (dx < -R || dx > R) continue;
+                    const size_t src = (size_t)(dy + R) * D + (dx + R);
+                    const size_t dst = ((size_t)(dy + R) * ng + k) * 8;
+                    gt[dst + q] = (T)tab.wc[src];
+                    gt[dst + 4 + q] = (T)tab.ws[src];
+                }
+    }
+    // The tables are staged synchronously: the workspace may still be read by
+    // earlier work on this stream, so wait for it first.
+    AMAP_HIP(hipStreamSynchronize(s), "stream synchronize before table upload");
+    char* pc = base + off_w;
+    char* ps = pc + wbytes;
+    char* pg = ps + wbytes;
+    AMAP_HIP(hipMemcpy(base, tab.half.data(), (size_t)D * sizeof(int), hipMemcpyHostToDevice),
+             "upload tap rows");
+    AMAP_HIP(hipMemcpy(pc, wc.data(), wc.size() * sizeof(T), hipMemcpyHostToDevice), "upload taps");
+    AMAP_HIP(hipMemcpy(ps, ws.data(), ws.size() * sizeof(T), hipMemcpyHostToDevice), "upload taps");
+    if (grouped)
+        AMAP_HIP(hipMemcpy(pg, gt.data(), gt.size() * sizeof(T), hipMemcpyHostToDevice), "upload tap groups");
+    AMAP_HIP(launch_map_direct<T>(logn, g1, g2, R, (const int*)base, (const T*)pc, (const T*)ps,
+                                  grouped ? (const T*)pg : nullptr, out, s),
+             "direct aperture-mass kernel");
+    return AMAP_OK;
+}
+
+extern "C" {
+
 amap_status amap_map_direct(amap_ctx_t c, amap_dtype dt, int n, const void* g1, const void* g2,
                             double theta_px, amap_filter filter, double fparam, double cut_px,
                             void* map_out, void* stream) {
@@ -1017,38 +1068,12 @@ amap_status amap_map_direct(amap_ctx_t c, amap_dtype dt, int n, const void* g1, 
     DeviceGuard g(c->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
     TimerScope ts(c);
-    const int D = 2 * tab.R + 1;
-    const size_t e = esize(dt);
-    const size_t off_w = align256((size_t)D * sizeof(int));
-    const size_t need = off_w + 2 * align256((size_t)D * D * e);
-    AMAP_TRY(c->ws.reserve(need));
-    char* base = static_cast<char*>(c->ws.ptr);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // The tables are staged synchronously: the workspace may still be read by
-    // earlier work on this stream, so wait for it first.
-    AMAP_HIP(hipStreamSynchronize(s), "stream synchronize before table upload");
-    AMAP_HIP(hipMemcpy(base, tab.half.data(), (size_t)D * sizeof(int), hipMemcpyHostToDevice),
-             "upload tap rows");
     const int logn = ilog2(n);
-    if (dt == AMAP_F32) {
-        std::vector<float> wc(tab.wc.begin(), tab.wc.end()), ws(tab.ws.begin(), tab.ws.end());
-        char* pc = base + off_w;
-        char* ps = pc + align256((size_t)D * D * 4);
-        AMAP_HIP(hipMemcpy(pc, wc.data(), wc.size() * 4, hipMemcpyHostToDevice), "upload taps");
-        AMAP_HIP(hipMemcpy(ps, ws.data(), ws.size() * 4, hipMemcpyHostToDevice), "upload taps");
-        AMAP_HIP(launch_map_direct<float>(logn, (const float*)g1, (const float*)g2, tab.R,
-                                          (const int*)base, (const float*)pc, (const float*)ps,
-                                          (float*)map_out, s), "direct aperture-mass kernel");
-    } else {
-        char* pc = base + off_w;
-        char* ps = pc + align256((size_t)D * D * 8);
-        AMAP_HIP(hipMemcpy(pc, tab.wc.data(), tab.wc.size() * 8, hipMemcpyHostToDevice), "upload taps");
-        AMAP_HIP(hipMemcpy(ps, tab.ws.data(), tab.ws.size() * 8, hipMemcpyHostToDevice), "upload taps");
-        AMAP_HIP(launch_map_direct<double>(logn, (const double*)g1, (const double*)g2, tab.R,
-                                           (const int*)base, (const double*)pc, (const double*)ps,
-                                           (double*)map_out, s), "direct aperture-mass kernel");
-    }
-    return AMAP_OK;
+    return dt == AMAP_F32
+        ? enqueue_direct<float>(c, tab, logn, (const float*)g1, (const float*)g2, (float*)map_out,
+                                static_cast<hipStream_t>(stream))
+        : enqueue_direct<double>(c, tab, logn, (const double*)g1, (const double*)g2, (double*)map_out,
+                                 static_cast<hipStream_t>(stream));
 }
 
 static amap_status validate_noise(amap_dtype dt, int n, int J, const void* g1, const void* g2,

@@ -303,14 +303,36 @@ struct FS {
     static constexpr int RR = N1 / N2;
 };
 
-// Threads and LDS of the four-step kernels
-template <typename T, int LOGN>
+// Threads and LDS of the four-step column kernels: strips of W columns,
+// at most 16 and at most 128 KiB of LDS; WREQ (if smaller) narrows the
+// strip so that a small batch still spreads over many workgroups.
+template <typename T, int LOGN, int WREQ = 0>
 struct Strip4 {
     static constexpr int N = 1 << LOGN;
     static constexpr int W0 = ((128 * 1024) / (int)sizeof(cpx<T>)) / N;
-    static constexpr int W = W0 > 16 ? 16 : W0;
+    static constexpr int WMAX = W0 > 16 ? 16 : W0;
+    static constexpr int W = (WREQ > 0 && WREQ < WMAX) ? WREQ : WMAX;
     static constexpr int NT = W * FS<LOGN>::N2;
 };
+
+// Strip s and map b of the column kernels' workgroup.  With `xcd` set,
+// workgroups are renumbered so that consecutive strips of a map run on one
+// XCD (the hardware deals workgroups out to the eight XCDs in turn): strips
+// whose row segments share a cache line then meet in one L2 instead of each
+// XCD fetching the whole line.  Not used where all maps read one shared
+// input (noise realisations), which each XCD keeps in its L2 as it is.
+__device__ __forceinline__ void strip_of(int xcd, int& s, int& b) {
+    s = blockIdx.x;
+    b = blockIdx.y;
+    const int nx = gridDim.x;
+    const int total = nx * gridDim.y;
+    if (xcd && (total & 7) == 0) {
+        const int l = blockIdx.x + nx * blockIdx.y;
+        const int v = (l & 7) * (total >> 3) + (l >> 3);
+        s = v % nx;
+        b = v / nx;
+    }
+}
 template <typename T, int LOGN>
 struct Row4 {
     static constexpr int N2 = FS<LOGN>::N2, N1 = FS<LOGN>::N1;
@@ -329,17 +351,19 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // ---- P1: load shears (optionally rotate), forward FFT along y (four-step) -------
-template <typename T, int LOGN, bool ROTATE>
-__global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
+template <typename T, int LOGN, bool ROTATE, int WREQ>
+__global__ void __launch_bounds__((Strip4<T, LOGN, WREQ>::NT))
 k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
               const long long* __restrict__ g1_off, const long long* __restrict__ g2_off,
-              cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0, const cpx<T>* __restrict__ tw) {
+              cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0, const cpx<T>* __restrict__ tw,
+              int xcd) {
     using F = FS<LOGN>;
-    using S = Strip4<T, LOGN>;
+    using S = Strip4<T, LOGN, WREQ>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W, NT = S::NT;
     __shared__ cpx<T> buf[N * W];
-    const int b = blockIdx.y;
-    const int x0 = blockIdx.x * W;
+    int sx, b;
+    strip_of(xcd, sx, b);
+    const int x0 = sx * W;
     const T* a1 = g1 + (g1_off ? g1_off[b] : (long long)b * g_stride);
     const T* a2 = g2 + (g2_off ? g2_off[b] : (long long)b * g_stride);
     if (ROTATE) {
@@ -742,17 +766,18 @@ k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw)
 }
 
 // ---- P3: inverse FFT along y (four-step), split real/imaginary -----------------
-template <typename T, int LOGN>
-__global__ void __launch_bounds__((Strip4<T, LOGN>::NT))
+template <typename T, int LOGN, int WREQ>
+__global__ void __launch_bounds__((Strip4<T, LOGN, WREQ>::NT))
 k_ks_cols_inv(const cpx<T>* __restrict__ C, long long in_stride, T* __restrict__ kE,
               T* __restrict__ kB, long long out_stride, int kB_count,
-              const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw) {
+              const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw, int xcd) {
     using F = FS<LOGN>;
-    using S = Strip4<T, LOGN>;
+    using S = Strip4<T, LOGN, WREQ>;
     constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W;
     __shared__ cpx<T> buf[N * W];
-    const int b = blockIdx.y;
-    const int x0 = blockIdx.x * W;
+    int sx, b;
+    strip_of(xcd, sx, b);
+    const int x0 = sx * W;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
     const cpx<T>* in = C + (long long)b * in_stride + x0 + c;
     cpx<T> a[N1];
@@ -797,6 +822,49 @@ constexpr bool pair_ok() {
            (size_t)RowPair<T, LOGN>::UNITS * 4 * Row4<T, LOGN>::EX * sizeof(cpx<T>) <= 65536;
 }
 
+// The four-step kernels with strips of WREQ columns.
+template <typename T, int LOGN, int WREQ>
+static hipError_t ks_launch_w(const KsArgs<T>& a) {
+    constexpr int N = 1 << LOGN;
+    using S = Strip4<T, LOGN, WREQ>;
+    using R = Row4<T, LOGN>;
+    const dim3 gs(N / S::W, a.batch), gr(N / R::LINES, a.batch);
+    // XCD grouping where strips read or write row segments narrower than a
+    // 128-byte line, except for a shared input (noise realisations)
+    const bool shared_in = a.g_stride == 0 && !a.g1_off && a.batch > 1;
+    const int xcd_in = (!shared_in && S::W * (int)sizeof(T) < 128) ? 1 : 0;
+    const int xcd_out = S::W * (int)sizeof(T) < 128 ? 1 : 0;
+    if (a.rotate)
+        AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
+                    k_ks_cols_fwd<T, LOGN, true, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                        a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw, xcd_in));
+    else
+        AMAP_LAUNCH("ks_cols_fwd", a.stream,
+                    k_ks_cols_fwd<T, LOGN, false, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                        a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw, xcd_in));
+    if constexpr (pair_ok<T, LOGN>()) {
+        if (a.pair_e) {
+            using RP = RowPair<T, LOGN>;
+            if (a.kE_off || a.batch < 1) return hipErrorInvalidValue;
+            const int pairs = (a.batch + 1) / 2;
+            AMAP_LAUNCH("ks_rows_pair", a.stream,
+                        k_ks_rows_pair<T, LOGN><<<dim3((N / 2) / RP::UNITS, pairs), RP::NT, 0, a.stream>>>(
+                            a.C, a.batch, a.tw));
+            AMAP_LAUNCH("ks_cols_inv_pair", a.stream,
+                        k_ks_cols_inv<T, LOGN, WREQ><<<dim3(N / S::W, pairs), S::NT, 0, a.stream>>>(
+                            a.C, 2ll * N * N, a.kE, a.kE + a.out_stride, 2 * a.out_stride,
+                            a.batch / 2, nullptr, a.tw, xcd_out));
+            return hipGetLastError();
+        }
+    }
+    AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
+    AMAP_LAUNCH("ks_cols_inv", a.stream,
+                k_ks_cols_inv<T, LOGN, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                    a.C, (long long)N * N, a.kE, a.pair_e ? nullptr : a.kB, a.out_stride, a.batch,
+                    a.kE_off, a.tw, xcd_out));
+    return hipGetLastError();
+}
+
 template <typename T, int LOGN>
 static hipError_t ks_launch_n(const KsArgs<T>& a) {
     constexpr int N = 1 << LOGN;
@@ -818,37 +886,18 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
                     k_ks_cols_inv_generic<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
                                                                                 a.out_stride, a.kE_off, a.tw));
     } else {
-        using S = Strip4<T, LOGN>;
-        using R = Row4<T, LOGN>;
-        const dim3 gs(N / S::W, a.batch), gr(N / R::LINES, a.batch);
-        if (a.rotate)
-            AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
-                        k_ks_cols_fwd<T, LOGN, true><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
-        else
-            AMAP_LAUNCH("ks_cols_fwd", a.stream,
-                        k_ks_cols_fwd<T, LOGN, false><<<gs, S::NT, 0, a.stream>>>(
-                            a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw));
-        if constexpr (pair_ok<T, LOGN>()) {
-            if (a.pair_e) {
-                using RP = RowPair<T, LOGN>;
-                if (a.kE_off || a.batch < 1) return hipErrorInvalidValue;
-                const int pairs = (a.batch + 1) / 2;
-                AMAP_LAUNCH("ks_rows_pair", a.stream,
-                            k_ks_rows_pair<T, LOGN><<<dim3((N / 2) / RP::UNITS, pairs), RP::NT, 0, a.stream>>>(
-                                a.C, a.batch, a.tw));
-                AMAP_LAUNCH("ks_cols_inv_pair", a.stream,
-                            k_ks_cols_inv<T, LOGN><<<dim3(N / S::W, pairs), S::NT, 0, a.stream>>>(
-                                a.C, 2ll * N * N, a.kE, a.kE + a.out_stride, 2 * a.out_stride,
-                                a.batch / 2, nullptr, a.tw));
-                return hipGetLastError();
-            }
+        // strip width: the widest (16, or what 128 KiB of LDS holds) unless
+        // the batch is too small to give the column passes ~512 workgroups
+        // at it; then narrower strips, down to 4 columns, from n = 256
+        int w = Strip4<T, LOGN>::W;
+        while (N >= 256 && w > 4 && (long long)(N / w) * a.batch < 512) w /= 2;
+        if constexpr (Strip4<T, LOGN>::W >= 16) {
+            if (w == 16) return ks_launch_w<T, LOGN, 16>(a);
         }
-        AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
-        AMAP_LAUNCH("ks_cols_inv", a.stream,
-                    k_ks_cols_inv<T, LOGN><<<gs, S::NT, 0, a.stream>>>(
-                        a.C, (long long)N * N, a.kE, a.pair_e ? nullptr : a.kB, a.out_stride, a.batch,
-                        a.kE_off, a.tw));
+        if constexpr (Strip4<T, LOGN>::W >= 8) {
+            if (w == 8) return ks_launch_w<T, LOGN, 8>(a);
+        }
+        return ks_launch_w<T, LOGN, 4>(a);
     }
     return hipGetLastError();
 }

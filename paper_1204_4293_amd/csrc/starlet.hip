@@ -323,6 +323,117 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
     xlo = rlo; xhi = rhi; vlo = clo; vhi = chi;
 }
 
+// Row pass A -> B of one dilation class for the noise stages: the nv
+// vectors of a row go to nv consecutive threads and the threads' row groups
+// (nrg of them) step down rows [0, nrows) of the pass, so a thread's items
+// lie at a fixed stride from its first one at `off`; every item is done for
+// each of the RB tiles (tstride apart).
+template <typename T, int RB, int DXC>
+__device__ __forceinline__ void row_pass_grid(const T* A, T* Bf, int off, int r, int nrows, int nrg,
+                                              int RS, int dx, int tstride) {
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    const int step = nrg * RS;
+    for (; r < nrows; r += nrg, off += step) {
+        VA o[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            const T* ra = A + t * tstride + off;
+            if constexpr (DXC != 0) {
+                const VA l = vload<T, G>(ra - G), c = vload<T, G>(ra), rr = vload<T, G>(ra + G);
+                T w[3 * G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
+                    o[t].e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
+                }
+            } else {
+                o[t] = vcombine<T, G>(vload<T, G>(ra - 2 * dx), vload<T, G>(ra - dx), vload<T, G>(ra),
+                                      vload<T, G>(ra + dx), vload<T, G>(ra + 2 * dx));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RB; ++t) vstore<T, G>(Bf + t * tstride + off, o[t]);
+    }
+}
+
+// Row and column passes of scale s of a noise stage on the RB tiles in A
+// (B is scratch), as tile_scale_pass computes them, with the items laid
+// out as a grid over the threads: in the row pass thread (rg, col) takes
+// vector col of rows rg, rg + nrg, ...; in the column pass window chains
+// q = rg, rg + nq, ... of vector column col, nq a multiple of the dilation
+// so that a thread's chains share one phase.  Per item only a constant
+// stride is added, instead of splitting an item index.
+template <typename T, int NT, int RB>
+__device__ __forceinline__ void tile_scale_pass_grid(T* A, T* Bf, const TileGeom& g, int s, int& xlo,
+                                                     int& xhi, int& vlo, int& vhi, int tstride) {
+    constexpr int G = Vec<T>::G;
+    using VA = VArr<T, G>;
+    const int tid = threadIdx.x;
+    const int RS = g.RS;
+    const int dx = g.d0 << s, dv = 1 << s;
+    const int rlo = xlo + 2 * dx, rhi = xhi - 2 * dx;
+    const int rlo4 = rlo / G * G;
+    const int nv = (rhi - rlo4 + G - 1) / G;   // vectors per row, <= TXT / G <= NT (host-checked)
+    // a row's vectors go to a multiple of 8 lanes, so that every group of
+    // eight lanes (one 128-byte LDS access) stays inside one row
+    const int nvp = (nv + 7) & ~7;
+    const int rg = fdiv(tid, 1.0f / (float)nvp);
+    const int col = tid - rg * nvp;
+    const int nrg = NT / nvp;
+    const int xoff = rlo4 + col * G;
+    if (rg < nrg && col < nv) {
+        const int off = (vlo + rg) * RS + xoff;
+        const int nrows = vhi - vlo;
+        if (dx == 1) {
+            row_pass_grid<T, RB, 1>(A, Bf, off, rg, nrows, nrg, RS, dx, tstride);
+        } else if (2 * dx <= G) {
+            if constexpr (G >= 4) row_pass_grid<T, RB, 2>(A, Bf, off, rg, nrows, nrg, RS, dx, tstride);
+        } else {
+            row_pass_grid<T, RB, 0>(A, Bf, off, rg, nrows, nrg, RS, dx, tstride);
+        }
+    }
+    lds_barrier();
+    const int clo = vlo + 2 * dv, chi = vhi - 2 * dv;
+    const int lmax = (chi - clo + dv - 1) / dv;
+    const int nseg = (lmax + kSegLen - 1) / kSegLen;
+    const int nchain = dv * nseg;            // window chains per vector column and tile
+    const int nq = nrg & ~(dv - 1);          // chains in flight per column, a multiple of dv
+    if (rg < nq && col < nv) {
+        // chain q of the RB tiles' RB * nchain: tile q / nchain, phase q mod dv
+        const int phase = rg & (dv - 1);
+        const int step = dv * RS;
+        for (int q = rg; q < RB * nchain; q += nq) {
+            int qq = q, tb = 0;
+            if (RB > 1 && qq >= nchain) { qq -= nchain; tb = tstride; }
+            const int vfirst = clo + phase + dv * ((qq >> s) * kSegLen);
+            if (vfirst >= chi) continue;
+            const T* wp = Bf + tb + xoff + (vfirst - 2 * dv) * RS;
+            T* op = A + tb + xoff + vfirst * RS;
+            VA win[kSegLen + 4];
+            if (vfirst + dv * (kSegLen - 1) < chi) {  // a whole segment
+#pragma unroll
+                for (int k = 0; k < kSegLen + 4; ++k) win[k] = vload<T, G>(wp + k * step);
+#pragma unroll
+                for (int k = 0; k < kSegLen; ++k)
+                    vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+            } else {
+#pragma unroll
+                for (int k = 0; k < kSegLen + 4; ++k)
+                    if (k < 4 || vfirst + dv * (k - 2) < chi + 2 * dv) win[k] = vload<T, G>(wp + k * step);
+#pragma unroll
+                for (int k = 0; k < kSegLen; ++k)
+                    if (vfirst + dv * k < chi)
+                        vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+            }
+        }
+    }
+    lds_barrier();
+    xlo = rlo; xhi = rhi; vlo = clo; vhi = chi;
+}
+
 // Owned vector k of the tile: its LDS offset and global offset in a plane.
 __device__ __forceinline__ int owned_lds(const TileGeom& g, int e) {
     return (g.Hv + (e >> g.log_tw)) * g.RS + g.Hx + (e & (g.tw - 1));
@@ -567,8 +678,7 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
             // three scales of sums leave no registers for a second row item
-            tile_scale_pass<T, NT, RB, NS == 3 && sizeof(T) == 4 ? 1 : 2>(A, Bf, g, s, xlo, xhi, vlo, vhi,
-                                                                          tstride);
+            tile_scale_pass_grid<T, NT, RB>(A, Bf, g, s, xlo, xhi, vlo, vhi, tstride);
             // realisations in order, so the update sequence matches one at a time
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
@@ -978,6 +1088,7 @@ static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, i
                 if (sizeof(T) == 8 && cfg.nt > 512) continue;  // no 1024-thread double stages
                 if (cfg.kv > 1 && ns == 3) continue;  // three scales of state for 4 vectors would spill
                 if ((TXT / G) * TVT > cfg.nt * noise_prefetch(cfg.nt, cfg.kv)) continue;
+                if (((TXT / G + 7) & ~7) > cfg.nt) continue;  // a tile row's vectors spread over the threads
             }
             insert(StageGeom{ns, nt, tw, th, lds, 1}, r);
             if (noise && sizeof(T) == 4 && ns <= 2) {
@@ -1068,6 +1179,7 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
         const int d0 = 1 << (a.j0 - 1);
         const int TXT = g.tw + 2 * stage_hx(d0, NS, G), TVT = g.th + 2 * 2 * ((1 << NS) - 1);
         if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV, RB) || g.tw * g.th > NT * KV * G ||
+            ((TXT / G + 7) & ~7) > NT ||
             g.lds < (size_t)(2 * RB * (TXT + 2 * G) * TVT + G) * sizeof(T))
             return hipErrorInvalidConfiguration;
     }

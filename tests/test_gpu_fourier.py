@@ -71,3 +71,51 @@ def test_fourier_response_of_the_filters(ctx):
     assert lobe["s98_l1"] > 1e-2 and lobe["jbj04_cut1"] > 1e-2
     assert 1e-3 < lobe["s98_l3"] < lobe["s98_l1"]
     assert lobe["starlet"] < 1e-4 and lobe["w2"] < 1e-6 and lobe["jbj04_cut5"] < 1e-6
+
+
+def b3_transfer(n, j):
+    """Fourier response of j starlet smoothing steps: the product of the
+    dilated B3 responses (6 + 8 cos w + 2 cos 2w) / 16 along x and y."""
+    w = 2.0 * np.pi * np.fft.fftfreq(n)
+    wy, wx = np.meshgrid(w, w, indexing="ij")
+    h = np.ones((n, n))
+    for i in range(j):
+        s = float(1 << i)
+        h *= ((6 + 8 * np.cos(s * wx) + 2 * np.cos(2 * s * wx)) / 16.0) * \
+             ((6 + 8 * np.cos(s * wy) + 2 * np.cos(2 * s * wy)) / 16.0)
+    return h
+
+
+def test_fourier_response_per_scale(ctx):
+    # Sec. 4.4, the figure of the wavelet filter's Fourier response against
+    # scale (J = 5): the GPU planes of a unit delta, transformed, are the
+    # per-scale responses; w_1 is a high-pass filter, w_2 .. w_4 band-pass
+    # filters whose peak frequency halves from scale to scale, c_4 a low-pass
+    # filter, and the responses add up to one (exact reconstruction)
+    n, J = 128, 5
+    d = np.zeros((n, n))
+    d[0, 0] = 1.0
+    planes = ctx.starlet_forward(torch.tensor(d, dtype=torch.float64, device="cuda"), J)
+    torch.cuda.synchronize()
+    p = planes.cpu().numpy()
+    assert np.max(np.abs(p - O.starlet_forward(d, J))) <= 1e-10 / n
+    resp = np.fft.fft2(p).real  # the impulse responses are even: real spectra
+    want = [b3_transfer(n, j - 1) - b3_transfer(n, j) for j in range(1, J)] + [b3_transfer(n, J - 1)]
+    for j in range(J):
+        assert np.max(np.abs(resp[j] - want[j])) <= 1e-12, j
+    assert np.max(np.abs(resp.sum(axis=0) - 1.0)) <= 1e-12
+    axis = resp[:, 0, : n // 2 + 1]  # along k_x at k_y = 0, from 0 to Nyquist
+    w1, c4 = axis[0], axis[J - 1]
+    assert abs(w1[0]) < 1e-12 and abs(w1[-1] - 1.0) < 1e-12                # w_1: high-pass
+    assert np.all(np.diff(w1) >= -1e-15)
+    assert abs(c4[0] - 1.0) < 1e-12 and np.max(c4[n // 16:]) < 1e-2         # c_4: low-pass
+    peaks = []
+    for j in range(1, J - 1):                                               # w_2 .. w_4: band-pass
+        a = axis[j]
+        k = int(np.argmax(a))
+        assert abs(a[0]) < 1e-12 and 0 < k < n // 2, j
+        assert np.all(np.diff(a[: k + 1]) >= -1e-15), j                     # one rise to the peak
+        assert np.max(a[3 * k:]) < 2e-2 * a[k], j                           # no high-frequency lobes
+        peaks.append(k)
+    for a, b in zip(peaks, peaks[1:]):
+        assert abs(a / b - 2.0) <= 0.35, peaks

@@ -253,6 +253,23 @@ def test_map_direct(ctx, filt, fparam, theta, cut, dtype):
     assert maxerr(host(got), ref) <= TOL[dtype] * rms(kE)
 
 
+@pytest.mark.parametrize("filt,fparam,theta,cut", [
+    (O.FILTER_STARLET, 0.0, 4.0, 0.0), (O.FILTER_STARLET, 0.0, 3.5, 7.3), (O.FILTER_S98, 2.0, 6.0, 6.0),
+    (O.FILTER_JBJ04, 1.0, 3.0, 0.0), (O.FILTER_STARLET, 0.0, 1.0, 1.0)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_map_direct_row_kernel(ctx, filt, fparam, theta, cut, dtype):
+    # maps from 512 px wide run the LDS row kernel (taps in groups of four
+    # dx, zero-padded outside the disc): whole-map parity at 512^2
+    n = 512
+    print("map_direct rows n=%d theta=%g cut=%g %s" % (n, theta, cut, dtype), flush=True)
+    _, g1, g2 = S.shear_map(n, 53, 54)
+    kE, _ = O.ks_invert(g1, g2)
+    ref = O.map_direct(g1, g2, theta, filt, fparam, cut)
+    got = ctx.map_direct(dev(g1, dtype), dev(g2, dtype), theta, filt, fparam, cut)
+    torch.cuda.synchronize()
+    assert maxerr(host(got), ref) <= TOL[dtype] * rms(kE)
+
+
 @pytest.mark.parametrize("theta", [2, 16, 64])
 def test_map_direct_full_size_sampled(ctx, theta):
     n = 1024
