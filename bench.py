@@ -47,6 +47,8 @@ FP32_NONPACKED_TFLOPS = 78.6
 
 N, J, R_REAL, SEED, THRESH = 1024, 7, 256, 23, 3.0
 TRAFFIC_PROFILE = "noise_path_1024_J7_R256_traffic.md"
+PLAIN_PROFILE = "plain_1024_J7_traffic.md"
+BATCHED_PROFILE = "uneven_batch_512_traffic.md"
 # tuned stage schedules of the bench's shapes, loaded instead of tuning live
 # (so that its kernels are exactly those of the committed profiles)
 SCHEDULES = "noise_path_1024_J7_R256_schedules.json"
@@ -173,22 +175,32 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, profile=TRAFFIC_PROFILE):
-    """HBM bytes per launch of ``kernel`` from a committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (each counter scaled by its reading for
-    a copy of known size), or None when that summary was taken on other
-    kernel sources or does not cover the kernel."""
+def profile_line(profile, key):
+    """The JSON value of the line ``key: ...`` of a committed rocprofv3
+    summary under profiles/, or None when the summary is missing, lacks the
+    line, or was taken on other kernel sources (its digest differs)."""
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
-    sha, table = None, None
+    sha, val = None, None
     with open(path) as f:
         for line in f:
             if line.startswith("kernel-sources-sha256:"):
                 sha = line.split(":", 1)[1].strip()
-            elif line.startswith("traffic-json:"):
-                table = json.loads(line.split(":", 1)[1])
-    if sha != kernel_sources_sha256() or not table or kernel not in table:
+            elif line.startswith(key + ":"):
+                val = json.loads(line.split(":", 1)[1])
+    if sha != kernel_sources_sha256():
+        return None
+    return val
+
+
+def measured_traffic(kernel, profile=TRAFFIC_PROFILE):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of the noise path (each counter scaled
+    by its reading for a copy of known size), or None when that summary was
+    taken on other kernel sources or does not cover the kernel."""
+    table = profile_line(profile, "traffic-json")
+    if not table or kernel not in table:
         return None
     return table[kernel]["bytes_per_launch"]
 
@@ -265,16 +277,22 @@ def _gen_map(args):
     return np.asarray(g1, dtype=np.float32), np.asarray(g2, dtype=np.float32)
 
 
+GEN_WORKERS = 16
+
+
 def generate_maps(specs):
     """synth.shear_map for each (n, grf_seed, noise_seed), spread over up to
-    16 worker processes; float32 arrays in the order given."""
+    GEN_WORKERS worker processes (1: in this process); float32 arrays in the
+    order given."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(16, cores, len(specs)))
+    cores = max(1, min(GEN_WORKERS, cores, len(specs)))
+    if cores == 1:
+        return [_gen_map(sp) for sp in specs]
     # largest first, so the pool ends together
     order = sorted(range(len(specs)), key=lambda i: -specs[i][0])
     out = [None] * len(specs)
@@ -339,12 +357,15 @@ def uneven_batch(ctx, reps):
     torch.cuda.synchronize()
     t_plain = e0.elapsed_time(e1) / max(1, reps // 2) * 1e-3
     plan.close()
+    meas = profile_line(BATCHED_PROFILE, "batched-bytes-per-run")
     counts = {str(n): sides.count(n) for n in sorted(set(sides))}
     return {"workload": "512 distinct float32 maps (seeds 1000+i), sides %s, J = log2 N - 2, "
                         "KS + starlet" % counts,
             "value": units / t_batched / 1e6, "unit": "Mpix·scales/s", "ms_per_batch": t_batched * 1e3,
             "hbm_alg_GBps": b_alg / t_batched / 1e9,
             "hbm_alg_frac": b_alg / t_batched / (HBM_PEAK_GBS * 1e9),
+            "hbm_meas_bytes": meas,
+            "hbm_meas_frac": meas / t_batched / (HBM_PEAK_GBS * 1e9) if meas else None,
             "bytes_alg": b_alg,
             "plain": {"value": units / t_plain / 1e6, "ms_per_batch": t_plain * 1e3,
                       "hbm_alg_frac": b_alg / t_plain / (HBM_PEAK_GBS * 1e9)}}
@@ -435,6 +456,41 @@ def served_stream(ctx, requests):
     return out
 
 
+def profile_workload(ctx, which, t1, t2):
+    """The fixed workloads of --profile (for counter runs): no timing."""
+    import torch
+
+    import synth
+    import paper_1204_4293_amd as amap
+    dev = t1.device
+    if which == "plain":
+        ke = torch.empty_like(t1)
+        pl = torch.empty((J, N, N), dtype=torch.float32, device=dev)
+        for _ in range(10):
+            ctx.ks_invert(t1, t2, kappa_e=ke)
+            ctx.starlet_forward(ke, J, planes=pl)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "plain", "maps": 10, "n": N, "J": J}), flush=True)
+        return 0
+    sides = synth.uneven_batch_sides(512, 31)
+    maps = generate_maps([(n, 1000 + i, 5000 + i) for i, n in enumerate(sides)])
+    jobs = []
+    for i, n in enumerate(sides):
+        g1, g2 = maps[i]
+        jobs.append({"g1": torch.from_numpy(g1).to(dev), "g2": torch.from_numpy(g2).to(dev),
+                     "planes": torch.empty((n.bit_length() - 3, n, n), dtype=torch.float32, device=dev)})
+    del maps
+    plan = amap.BatchPlan(ctx, jobs)  # one direct run at creation
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run()  # capture, launch
+        plan.run()
+    side.synchronize()
+    plan.close()
+    print(json.dumps({"profile": "batched", "maps": len(jobs), "runs": 3}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +500,13 @@ def main():
                     help="budget of the oracle's timed sample (0 to skip)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-batch and served-stream measurements (profiler runs)")
+    ap.add_argument("--profile", choices=("plain", "batched"), default=None,
+                    help="only run a fixed workload for a profiler's counters: 'plain' = 10 "
+                         "single-map KS + starlet (J=7) sequences on the 1024^2 map, 'batched' = "
+                         "the uneven batch's plan (one run at creation, two graph runs)")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes generating the batched and served inputs (1: none; for "
+                         "profiler runs, whose preload would follow the workers)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests at each load level of the served stream (0 skips the stream)")
     ap.add_argument("--schedules", default=os.path.join(ROOT, "profiles", SCHEDULES),
@@ -455,6 +518,8 @@ def main():
                     help="also run one 256 MiB device copy (a kernel of known traffic for "
                          "scaling hardware byte counters)")
     args = ap.parse_args()
+    global GEN_WORKERS
+    GEN_WORKERS = max(1, args.gen_workers)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the "
               "multi-GPU sharding is a design, not built" % args.gpus, file=sys.stderr)
@@ -476,6 +541,8 @@ def main():
         with open(args.schedules) as f:
             ctx.plans_load(f.read())
         schedules_source = os.path.relpath(args.schedules, ROOT)
+    if args.profile:
+        return profile_workload(ctx, args.profile, t1, t2)
     out = {
         "kappa_e": torch.empty((N, N), dtype=torch.float32, device=dev),
         "planes": torch.empty((J, N, N), dtype=torch.float32, device=dev),
@@ -536,8 +603,8 @@ def main():
     dom_avg_s = live[dom][1] / live[dom][0] * 1e-3
     b_alg, f_alg = kernel_model(dom, N, J, B, starts)
     step_flops = 0.0
-    step_traffic = 0.0
-    traffic_complete = True
+    loop_traffic = 0.0
+    loop_complete = True
     for name, rec in kernels.items():
         bb, ff = kernel_model(name, N, J, B, starts)
         if bb is not None:
@@ -551,9 +618,11 @@ def main():
         tb = measured_traffic(name)
         if tb is not None:
             rec["hbm_meas_GBps"] = tb / (rec["avg_us"] * 1e-6) / 1e9
-            step_traffic += tb * rec["launches_per_step"]
-        else:
-            traffic_complete = False
+        if name in NOISE_KERNELS or name.startswith("noise_stage_j"):
+            if tb is None:
+                loop_complete = False
+            else:
+                loop_traffic += tb * rec["launches_per_step"]
     traffic = measured_traffic(dom)
     roofline = {"kernel": dom}
     roofline.update(roofline_of(dom, N, J, B, starts, dom_avg_s))
@@ -569,12 +638,15 @@ def main():
         "hbm_meas_frac": traffic / dom_avg_s / (HBM_PEAK_GBS * 1e9) if traffic else None,
         "traffic_over_design_bytes": traffic / b_alg if (traffic and b_alg) else None,
     })
+    # the whole step's algorithmic flops per second, and the counters' HBM
+    # bytes of the noise loop's kernels (everything but the signal's one-map
+    # kernels, finalize and peak count: ~2% of the step) per step
     step = {"alg_TFLOPs": step_flops / (ms_per_step * 1e-3) / 1e12,
             "alg_flops": step_flops,
             "frac_fp32": step_flops / (ms_per_step * 1e-3) / (FP32_PEAK_TFLOPS * 1e12),
-            "hbm_meas_bytes": step_traffic if traffic_complete else None,
-            "hbm_meas_frac": (step_traffic / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
-                              if traffic_complete else None)}
+            "noise_loop_hbm_meas_bytes": loop_traffic if loop_complete else None,
+            "noise_loop_hbm_meas_frac": (loop_traffic / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                                         if loop_complete else None)}
 
     # plain path: one map, KS + starlet, one launch sequence per map
     ke = out["kappa_e"]
@@ -595,6 +667,9 @@ def main():
     plain = {"value": N * N * J / (plain_ms * 1e-3) / 1e6, "unit": "Mpix·scales/s",
              "ms_per_map": plain_ms,
              "hbm_alg_frac": b_alg_map / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    meas = profile_line(PLAIN_PROFILE, "plain-bytes-per-map")
+    plain["hbm_meas_bytes"] = meas
+    plain["hbm_meas_frac"] = meas / (plain_ms * 1e-3) / (HBM_PEAK_GBS * 1e9) if meas else None
 
     # direct aperture mass vs the starlet on the 1024^2 map: map_direct at
     # theta = 2..64 px with the starlet filter truncated at cut = theta, vs
