@@ -53,3 +53,4 @@ from .bounded import (  # noqa: F401
     BC_PERIODIC, BC_MIRROR, BC_ZERO, boundary_index, smooth_step_bc, starlet_forward_bc,
     even_extension, ks_invert_padded, noise_sigma_bc, count_peaks_bc,
 )
+from .masks import mask_shear, count_peaks_masked, count_peaks_masked_planes  # noqa: F401

@@ -15,7 +15,11 @@ available, so seeded Gaussian random fields stand in for them):
   * shear from kappa through the lensing potential psi (kappa = lap(psi)/2):
     gamma1 = (psi_11 - psi_22)/2, gamma2 = psi_12, evaluated spectrally on
     the periodic grid -- each component is a real field built separately;
-  * shape noise: independent N(0, 0.3/sqrt(20)) on each of gamma1, gamma2.
+  * shape noise: independent N(0, 0.3/sqrt(20)) on each of gamma1, gamma2;
+  * survey masks (missing data, end of Sec. 5): discs cut out around bright
+    stars, radii log-uniform in [1.5, 12] pixels at uniform positions until
+    about ``frac`` of the field is covered, plus one bad column and one bad
+    row of pixels at seeded positions.
 
 White noise comes from numpy's PCG64 seeded with the given integer seed.
 """
@@ -127,3 +131,23 @@ def served_stream(count, qps, seed_arrivals=41, seed_sides=42):
     times = np.cumsum(gaps) - gaps[0]
     sides = [int(1 << int(e)) for e in rs.integers(8, 13, size=count)]
     return times, sides
+
+
+def survey_mask(ny, nx, seed, frac=0.1):
+    """Seeded observed/missing mask (uint8, 1 = observed) of an ny x nx field:
+    star discs covering about ``frac`` of the area, one bad column, one bad row."""
+    rng = np.random.default_rng(seed)
+    m = np.ones((ny, nx), dtype=np.uint8)
+    missing, target = 0, frac * ny * nx
+    while missing < target:
+        r = math.exp(rng.uniform(math.log(1.5), math.log(12.0)))
+        cy, cx = rng.uniform(0, ny), rng.uniform(0, nx)
+        y0, y1 = max(0, int(cy - r)), min(ny, int(cy + r) + 2)
+        x0, x1 = max(0, int(cx - r)), min(nx, int(cx + r) + 2)
+        yy, xx = np.mgrid[y0:y1, x0:x1]
+        hit = ((yy - cy) ** 2 + (xx - cx) ** 2 <= r * r) & (m[y0:y1, x0:x1] != 0)
+        m[y0:y1, x0:x1][hit] = 0
+        missing += int(np.count_nonzero(hit))
+    m[:, int(rng.integers(0, nx))] = 0
+    m[int(rng.integers(0, ny)), :] = 0
+    return m
