@@ -27,6 +27,26 @@
 
 namespace amap {
 
+// K consecutive values at p (16-byte aligned) through 16-byte loads.
+template <typename T, int K>
+__device__ __forceinline__ void load16(const T* __restrict__ p, T (&out)[K]) {
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int i = 0; i < K / 4; ++i) {
+            const f4 v = reinterpret_cast<const f4*>(p)[i];
+            out[4 * i] = v[0]; out[4 * i + 1] = v[1]; out[4 * i + 2] = v[2]; out[4 * i + 3] = v[3];
+        }
+    } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const d2 v = reinterpret_cast<const d2*>(p)[i];
+            out[2 * i] = v[0]; out[2 * i + 1] = v[1];
+        }
+    }
+}
+
 // ---- in-LDS Stockham FFT ---------------------------------------------------
 // Element (line l, index i) of LINES interleaved lines of length 2^LOGN
 // lives at buf[i*IS + l*LS].  NT threads cooperate.  Each stage reads all of
@@ -303,17 +323,40 @@ struct FS {
     static constexpr int RR = N1 / N2;
 };
 
-// Threads and LDS of the four-step column kernels: strips of W columns,
-// at most 16 and at most 128 KiB of LDS; WREQ (if smaller) narrows the
-// strip so that a small batch still spreads over many workgroups.
-template <typename T, int LOGN, int WREQ = 0>
+// Threads and LDS of the four-step column kernels: strips of W columns, N2
+// threads per column; WREQ (if smaller) narrows the strip so that a small
+// batch still spreads over many workgroups.  A strip's N x W values pass
+// through LDS in PH phases of N / PH rows (loads) and N1 / PH first-step
+// outputs (exchange).
+//   forward (FWD): up to 16 columns and 512 threads.  Where a thread's
+//     first-step DFT fits half the register file (FP32, N1 <= 32) the
+//     phases keep LDS at 64 KiB and the kernel is built for two workgroups
+//     per CU; otherwise LDS is held to 128 KiB at one workgroup per CU;
+//   inverse: as many columns (up to 16) as 128 KiB of LDS holds in one
+//     phase.  Its first step loads straight from memory and keeps many
+//     values in flight, so neither a register cap nor narrower phases pay.
+template <typename T, int LOGN, bool FWD, int WREQ = 0>
 struct Strip4 {
-    static constexpr int N = 1 << LOGN;
-    static constexpr int W0 = ((128 * 1024) / (int)sizeof(cpx<T>)) / N;
-    static constexpr int WMAX = W0 > 16 ? 16 : W0;
+    static constexpr int N = 1 << LOGN, N1 = FS<LOGN>::N1, N2 = FS<LOGN>::N2;
+    static constexpr int CPX = (int)sizeof(cpx<T>);
+    static constexpr int WT = 512 / N2 > 16 ? 16 : 512 / N2;
+    static constexpr int WL = (128 * 1024 / CPX) / N > 16 ? 16 : (128 * 1024 / CPX) / N;
+    static constexpr int WMAX = FWD ? WT : WL;
     static constexpr int W = (WREQ > 0 && WREQ < WMAX) ? WREQ : WMAX;
-    static constexpr int NT = W * FS<LOGN>::N2;
+    static constexpr int NT = W * N2;
+    static constexpr bool TWO = FWD && sizeof(T) == 4 && N1 <= 32 && NT >= 256;
+    static constexpr int CAP = TWO ? 64 * 1024 : 128 * 1024;
+    static constexpr int BYTES = N * W * CPX;
+    static constexpr int PH0 = BYTES <= CAP ? 1 : BYTES / CAP;
+    static constexpr int PH = PH0 > N1 ? N1 : PH0;
+    static constexpr int LDS = N * W / PH;  // complex values
+    static constexpr int MINW = TWO ? 2 * NT / 256 : 1;  // waves per SIMD for two workgroups
+    static_assert(N1 % PH == 0, "phases split the first-step index evenly");
 };
+template <typename T, int LOGN, int WREQ = 0>
+using StripF = Strip4<T, LOGN, true, WREQ>;
+template <typename T, int LOGN, int WREQ = 0>
+using StripI = Strip4<T, LOGN, false, WREQ>;
 
 // Strip s and map b of the column kernels' workgroup.  With `xcd` set,
 // workgroups are renumbered so that consecutive strips of a map run on one
@@ -352,68 +395,92 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ---- P1: load shears (optionally rotate), forward FFT along y (four-step) -------
 template <typename T, int LOGN, bool ROTATE, int WREQ>
-__global__ void __launch_bounds__((Strip4<T, LOGN, WREQ>::NT))
+__global__ void __launch_bounds__((StripF<T, LOGN, WREQ>::NT), (StripF<T, LOGN, WREQ>::MINW))
 k_ks_cols_fwd(const T* __restrict__ g1, const T* __restrict__ g2, long long g_stride,
               const long long* __restrict__ g1_off, const long long* __restrict__ g2_off,
               cpx<T>* __restrict__ C, uint64_t seed, uint64_t r0, const cpx<T>* __restrict__ tw,
               int xcd) {
     using F = FS<LOGN>;
-    using S = Strip4<T, LOGN, WREQ>;
-    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W, NT = S::NT;
-    __shared__ cpx<T> buf[N * W];
+    using S = StripF<T, LOGN, WREQ>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W, NT = S::NT, PH = S::PH;
+    constexpr int ROWS = N / PH, K = N1 / PH;  // rows and first-step indices per phase
+    __shared__ cpx<T> buf[S::LDS];
     int sx, b;
     strip_of(xcd, sx, b);
     const int x0 = sx * W;
     const T* a1 = g1 + (g1_off ? g1_off[b] : (long long)b * g_stride);
     const T* a2 = g2 + (g2_off ? g2_off[b] : (long long)b * g_stride);
-    if (ROTATE) {
-        // one Philox block covers 8 consecutive pixels of a row
-        constexpr int OCT_PER_ROW = (W + 7) / 8;
-        const uint64_t r = r0 + b;
-        for (int o = threadIdx.x; o < N * OCT_PER_ROW; o += NT) {
-            const int y = o / OCT_PER_ROW;
-            const int cx = (o % OCT_PER_ROW) * 8;
-            const int xa = (W >= 8) ? (x0 + cx) : (x0 & ~7);
-            const uint64_t pix = (uint64_t)y * N + xa;
-            uint32_t u[8];
-            philox_block_u32(seed, r, pix >> 3, u);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int x = xa + i;
-                if (W < 8 && (x < x0 || x >= x0 + W)) continue;
-                T p = a1[(long long)y * N + x], q = a2[(long long)y * N + x];
-                rotate_by_u32(u[i], p, q);
-                buf[y * W + (x - x0)] = make_cpx(p, q);
-            }
-        }
-    } else {
-        for (int e = threadIdx.x; e < N * W; e += NT) {
-            const int y = e / W, c = e % W;
-            const long long gi = (long long)y * N + x0 + c;
-            buf[e] = make_cpx(a1[gi], a2[gi]);
-        }
-    }
-    __syncthreads();
+    constexpr int G = 16 / (int)sizeof(T);  // values per 16-byte load
     const int c = threadIdx.x % W, t = threadIdx.x / W;
+    // row y = N2 n1 + t of column c goes to a[n1]; phase p stages rows
+    // p ROWS .. (p+1) ROWS - 1, i.e. n1 = p K .. (p+1) K - 1
     cpx<T> a[N1];
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) a[n1] = buf[(N2 * n1 + t) * W + c];
+    for (int p = 0; p < PH; ++p) {
+        const int y0 = p * ROWS;
+        if (p > 0) __syncthreads();  // the previous phase's reads are done
+        if (ROTATE) {
+            // one Philox block covers 8 consecutive pixels of a row
+            constexpr int OCT_PER_ROW = (W + 7) / 8;
+            const uint64_t r = r0 + b;
+            for (int o = threadIdx.x; o < ROWS * OCT_PER_ROW; o += NT) {
+                const int yl = o / OCT_PER_ROW, y = y0 + yl;
+                const int cx = (o % OCT_PER_ROW) * 8;
+                const int xa = (W >= 8) ? (x0 + cx) : (x0 & ~7);
+                const uint64_t pix = (uint64_t)y * N + xa;
+                uint32_t u[8];
+                philox_block_u32(seed, r, pix >> 3, u);
+                T gp[8], gq[8];
+                load16<T, 8>(a1 + (long long)y * N + xa, gp);
+                load16<T, 8>(a2 + (long long)y * N + xa, gq);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int x = xa + i;
+                    if (W < 8 && (x < x0 || x >= x0 + W)) continue;
+                    rotate_by_u32(u[i], gp[i], gq[i]);
+                    buf[yl * W + (x - x0)] = make_cpx(gp[i], gq[i]);
+                }
+            }
+        } else {
+            // G consecutive columns of a row per load
+            for (int e = threadIdx.x; e < ROWS * (W / G); e += NT) {
+                const int yl = e / (W / G), cc = (e % (W / G)) * G;
+                const long long gi = (long long)(y0 + yl) * N + x0 + cc;
+                T gp[G], gq[G];
+                load16<T, G>(a1 + gi, gp);
+                load16<T, G>(a2 + gi, gq);
+#pragma unroll
+                for (int i = 0; i < G; ++i) buf[yl * W + cc + i] = make_cpx(gp[i], gq[i]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n1 = 0; n1 < K; ++n1) a[p * K + n1] = buf[(N2 * n1 + t) * W + c];
+    }
     dft_reg<T, N1, false>(a);
     twiddle_powers<T, LOGN, false, N1>(tw, t, [&](int k1, const cpx<T>& w) { a[k1] = cmul(a[k1], w); });
-    __syncthreads();
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 * N2 + t) * W + c] = a[k1];
-    __syncthreads();
     cpx<T>* out = C + (long long)b * N * N + x0 + c;
+    // exchange phase q: first-step outputs k1 = q K .. (q+1) K - 1, then the
+    // second step over n2 for each (k1, column) of the phase
 #pragma unroll
-    for (int r = 0; r < F::RR; ++r) {
-        const int k1 = t + N2 * r;
-        cpx<T> v[N2];
+    for (int q = 0; q < PH; ++q) {
+        __syncthreads();  // LDS free
 #pragma unroll
-        for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(k1 * N2 + n2) * W + c];
-        dft_reg<T, N2, false>(v);
+        for (int kl = 0; kl < K; ++kl) buf[(kl * N2 + t) * W + c] = a[q * K + kl];
+        __syncthreads();
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) store_stream(&out[(long long)(k1 + N1 * k2) * N], v[k2]);
+        for (int r = 0; r < (K + N2 - 1) / N2; ++r) {
+            const int kl = t + N2 * r;
+            if (K % N2 == 0 || kl < K) {
+                cpx<T> v[N2];
+#pragma unroll
+                for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(kl * N2 + n2) * W + c];
+                dft_reg<T, N2, false>(v);
+                const int k1 = q * K + kl;
+#pragma unroll
+                for (int k2 = 0; k2 < N2; ++k2) store_stream(&out[(long long)(k1 + N1 * k2) * N], v[k2]);
+            }
+        }
     }
 }
 
@@ -767,14 +834,14 @@ k_ks_rows_pair(cpx<T>* __restrict__ C, int batch, const cpx<T>* __restrict__ tw)
 
 // ---- P3: inverse FFT along y (four-step), split real/imaginary -----------------
 template <typename T, int LOGN, int WREQ>
-__global__ void __launch_bounds__((Strip4<T, LOGN, WREQ>::NT))
+__global__ void __launch_bounds__((StripI<T, LOGN, WREQ>::NT), (StripI<T, LOGN, WREQ>::MINW))
 k_ks_cols_inv(const cpx<T>* __restrict__ C, long long in_stride, T* __restrict__ kE,
               T* __restrict__ kB, long long out_stride, int kB_count,
               const long long* __restrict__ kE_off, const cpx<T>* __restrict__ tw, int xcd) {
     using F = FS<LOGN>;
-    using S = Strip4<T, LOGN, WREQ>;
-    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W;
-    __shared__ cpx<T> buf[N * W];
+    using S = StripI<T, LOGN, WREQ>;
+    constexpr int N = F::N, N1 = F::N1, N2 = F::N2, W = S::W, PH = S::PH, K = N1 / PH;
+    __shared__ cpx<T> buf[S::LDS];
     int sx, b;
     strip_of(xcd, sx, b);
     const int x0 = sx * W;
@@ -784,25 +851,32 @@ k_ks_cols_inv(const cpx<T>* __restrict__ C, long long in_stride, T* __restrict__
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) a[n1] = in[(long long)(N2 * n1 + t) * N];
     dft_reg<T, N1, true>(a);
-    buf[t * W + c] = a[0];
-    twiddle_powers<T, LOGN, true, N1>(tw, t, [&](int k1, const cpx<T>& w) {
-        buf[(k1 * N2 + t) * W + c] = cmul(a[k1], w);
-    });
-    __syncthreads();
+    twiddle_powers<T, LOGN, true, N1>(tw, t, [&](int k1, const cpx<T>& w) { a[k1] = cmul(a[k1], w); });
     T* oe = kE + (kE_off ? kE_off[b] : (long long)b * out_stride) + x0 + c;
     T* ob = (kB && b < kB_count) ? kB + (long long)b * out_stride + x0 + c : nullptr;
+    // exchange in PH phases of K first-step outputs each, as the forward pass
 #pragma unroll
-    for (int r = 0; r < F::RR; ++r) {
-        const int k1 = t + N2 * r;
-        cpx<T> v[N2];
+    for (int q = 0; q < PH; ++q) {
+        if (q > 0) __syncthreads();  // the previous phase's reads are done
 #pragma unroll
-        for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(k1 * N2 + n2) * W + c];
-        dft_reg<T, N2, true>(v);
+        for (int kl = 0; kl < K; ++kl) buf[(kl * N2 + t) * W + c] = a[q * K + kl];
+        __syncthreads();
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-            const long long gi = (long long)(k1 + N1 * k2) * N;
-            oe[gi] = v[k2].x;
-            if (ob) ob[gi] = v[k2].y;
+        for (int r = 0; r < (K + N2 - 1) / N2; ++r) {
+            const int kl = t + N2 * r;
+            if (K % N2 == 0 || kl < K) {
+                cpx<T> v[N2];
+#pragma unroll
+                for (int n2 = 0; n2 < N2; ++n2) v[n2] = buf[(kl * N2 + n2) * W + c];
+                dft_reg<T, N2, true>(v);
+                const int k1 = q * K + kl;
+#pragma unroll
+                for (int k2 = 0; k2 < N2; ++k2) {
+                    const long long gi = (long long)(k1 + N1 * k2) * N;
+                    oe[gi] = v[k2].x;
+                    if (ob) ob[gi] = v[k2].y;
+                }
+            }
         }
     }
 }
@@ -826,21 +900,22 @@ constexpr bool pair_ok() {
 template <typename T, int LOGN, int WREQ>
 static hipError_t ks_launch_w(const KsArgs<T>& a) {
     constexpr int N = 1 << LOGN;
-    using S = Strip4<T, LOGN, WREQ>;
+    using SF = StripF<T, LOGN, WREQ>;
+    using SI = StripI<T, LOGN, WREQ>;
     using R = Row4<T, LOGN>;
-    const dim3 gs(N / S::W, a.batch), gr(N / R::LINES, a.batch);
+    const dim3 gf(N / SF::W, a.batch), gi(N / SI::W, a.batch), gr(N / R::LINES, a.batch);
     // XCD grouping where strips read or write row segments narrower than a
     // 128-byte line, except for a shared input (noise realisations)
     const bool shared_in = a.g_stride == 0 && !a.g1_off && a.batch > 1;
-    const int xcd_in = (!shared_in && S::W * (int)sizeof(T) < 128) ? 1 : 0;
-    const int xcd_out = S::W * (int)sizeof(T) < 128 ? 1 : 0;
+    const int xcd_in = (!shared_in && SF::W * (int)sizeof(T) < 128) ? 1 : 0;
+    const int xcd_out = SI::W * (int)sizeof(T) < 128 ? 1 : 0;
     if (a.rotate)
         AMAP_LAUNCH("ks_cols_fwd_rotate", a.stream,
-                    k_ks_cols_fwd<T, LOGN, true, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                    k_ks_cols_fwd<T, LOGN, true, WREQ><<<gf, SF::NT, 0, a.stream>>>(
                         a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw, xcd_in));
     else
         AMAP_LAUNCH("ks_cols_fwd", a.stream,
-                    k_ks_cols_fwd<T, LOGN, false, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                    k_ks_cols_fwd<T, LOGN, false, WREQ><<<gf, SF::NT, 0, a.stream>>>(
                         a.g1, a.g2, a.g_stride, a.g1_off, a.g2_off, a.C, a.seed, a.r0, a.tw, xcd_in));
     if constexpr (pair_ok<T, LOGN>()) {
         if (a.pair_e) {
@@ -851,7 +926,7 @@ static hipError_t ks_launch_w(const KsArgs<T>& a) {
                         k_ks_rows_pair<T, LOGN><<<dim3((N / 2) / RP::UNITS, pairs), RP::NT, 0, a.stream>>>(
                             a.C, a.batch, a.tw));
             AMAP_LAUNCH("ks_cols_inv_pair", a.stream,
-                        k_ks_cols_inv<T, LOGN, WREQ><<<dim3(N / S::W, pairs), S::NT, 0, a.stream>>>(
+                        k_ks_cols_inv<T, LOGN, WREQ><<<dim3(N / SI::W, pairs), SI::NT, 0, a.stream>>>(
                             a.C, 2ll * N * N, a.kE, a.kE + a.out_stride, 2 * a.out_stride,
                             a.batch / 2, nullptr, a.tw, xcd_out));
             return hipGetLastError();
@@ -859,7 +934,7 @@ static hipError_t ks_launch_w(const KsArgs<T>& a) {
     }
     AMAP_LAUNCH("ks_rows", a.stream, k_ks_rows<T, LOGN><<<gr, R::NT, 0, a.stream>>>(a.C, a.tw));
     AMAP_LAUNCH("ks_cols_inv", a.stream,
-                k_ks_cols_inv<T, LOGN, WREQ><<<gs, S::NT, 0, a.stream>>>(
+                k_ks_cols_inv<T, LOGN, WREQ><<<gi, SI::NT, 0, a.stream>>>(
                     a.C, (long long)N * N, a.kE, a.pair_e ? nullptr : a.kB, a.out_stride, a.batch,
                     a.kE_off, a.tw, xcd_out));
     return hipGetLastError();
@@ -886,15 +961,18 @@ static hipError_t ks_launch_n(const KsArgs<T>& a) {
                     k_ks_cols_inv_generic<T, LOGN><<<gs, S::NT, 0, a.stream>>>(a.C, a.kE, a.kB,
                                                                                 a.out_stride, a.kE_off, a.tw));
     } else {
-        // strip width: the widest (16, or what 128 KiB of LDS holds) unless
-        // the batch is too small to give the column passes ~512 workgroups
-        // at it; then narrower strips, down to 4 columns, from n = 256
-        int w = Strip4<T, LOGN>::W;
+        // strip width: the widest unless the batch is too small to give the
+        // column passes ~512 workgroups at it; then narrower strips, down to
+        // 4 columns, from n = 256 (each pass caps the request at its own
+        // widest strip)
+        constexpr int WMAX = StripF<T, LOGN>::W > StripI<T, LOGN>::W ? StripF<T, LOGN>::W
+                                                                     : StripI<T, LOGN>::W;
+        int w = WMAX;
         while (N >= 256 && w > 4 && (long long)(N / w) * a.batch < 512) w /= 2;
-        if constexpr (Strip4<T, LOGN>::W >= 16) {
+        if constexpr (WMAX >= 16) {
             if (w == 16) return ks_launch_w<T, LOGN, 16>(a);
         }
-        if constexpr (Strip4<T, LOGN>::W >= 8) {
+        if constexpr (WMAX >= 8) {
             if (w == 8) return ks_launch_w<T, LOGN, 8>(a);
         }
         return ks_launch_w<T, LOGN, 4>(a);
