@@ -249,6 +249,33 @@ amap_status amap_count_peaks_bc(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, i
                                 int boundary, const void* planes, double threshold,
                                 long long* counts_dev, void* stream);
 
+/*
+ * Masked fields (missing data inside the field: stars and bad pixels cut out
+ * of the image, end of Sec. 5, where the paper notes that plain
+ * reconstruction does not recover the lost information).  mask: ny*nx bytes,
+ * row-major, non-zero where the pixel is observed and 0 where it is missing,
+ * 256-byte aligned device memory.
+ *
+ * amap_mask_shear: g1_out = g1 and g2_out = g2 where observed, 0 where
+ * missing (ny*nx each).  An output may be its own input (in place);
+ * otherwise outputs overlap nothing.  The masked field then goes through
+ * amap_ks_invert_padded / amap_noise_maps_bc (or the periodic calls for a
+ * power-of-two square): a missing pixel carries no shear in the signal or in
+ * any noise realisation, since a rotation keeps a zero shear zero.
+ *
+ * amap_count_peaks_masked: peaks as amap_count_peaks_bc, counted only where
+ * the pixel and each of its 8 neighbours that the edge rule keeps inside the
+ * field are observed (a maximum that touches missing data is not counted;
+ * under AMAP_BC_ZERO a neighbour outside the field does not veto).  mask is
+ * the same for every plane.  counts_dev: nplanes long long, overwritten.
+ */
+amap_status amap_mask_shear(amap_ctx_t ctx, amap_dtype dt, int ny, int nx,
+                            const unsigned char* mask, const void* g1, const void* g2,
+                            void* g1_out, void* g2_out, void* stream);
+amap_status amap_count_peaks_masked(amap_ctx_t ctx, amap_dtype dt, int ny, int nx, int nplanes,
+                                    int boundary, const void* planes, const unsigned char* mask,
+                                    double threshold, long long* counts_dev, void* stream);
+
 /* Exact inverse of the decomposition (Sec. 3): kappa_out = c_{J-1} + sum w_j.
  * planes: J*n*n; kappa_out: n*n (may not overlap planes). */
 amap_status amap_starlet_reconstruct(amap_ctx_t ctx, amap_dtype dt, int n, int J,
@@ -373,10 +400,16 @@ typedef struct {
  * noise (n_real == 0) of one (n, J) are grouped: each group (in chunks of at
  * most 2 GiB of workspace) runs as one launch per kernel over all its maps,
  * which the kernels address through device tables of per-map pointers built
- * here.  Jobs with noise run one after another.  The plan owns its workspace
- * and tables (independent of the context's) and a captured HIP graph per
- * stream; it keeps the job pointers until destroyed, and the caller keeps
- * the buffers alive and unshared between jobs. */
+ * here.  Jobs with noise (and shapes without grouped kernels) run alone, on
+ * up to four lanes with a workspace region each (as many as fit 16 GiB of
+ * workspace; each job to the lane with the least work so far): in the
+ * captured graph of a non-null stream the lanes are branches forked from
+ * and joined back into that stream, so their jobs overlap on the device;
+ * on the null stream the lanes run one after another.  Results do not
+ * depend on the lane.  The plan owns its workspace, tables, lane streams
+ * and a captured HIP graph per stream; it keeps the job pointers until
+ * destroyed, and the caller keeps the buffers alive and unshared between
+ * jobs. */
 amap_status amap_batch_plan(amap_ctx_t ctx, amap_dtype dt, const amap_job* jobs,
                             int njobs, amap_plan_t* out);
 

@@ -82,6 +82,8 @@ def load():
         "amap_ks_invert_padded": (I, [P, I, I, I, I, P, P, P, P, P]),
         "amap_noise_maps_bc": (I, [P, I, I, I, I, I, I, P, P, I, U64, P, P, P, P]),
         "amap_count_peaks_bc": (I, [P, I, I, I, I, I, P, D, P, P]),
+        "amap_count_peaks_masked": (I, [P, I, I, I, I, I, P, P, D, P, P]),
+        "amap_mask_shear": (I, [P, I, I, I, P, P, P, P, P, P]),
         "amap_starlet_reconstruct": (I, [P, I, I, I, P, P, P]),
         "amap_map_direct": (I, [P, I, I, P, P, D, I, D, D, P, P]),
         "amap_noise_maps": (I, [P, I, I, I, P, P, I, U64, P, P, P, P]),
@@ -285,6 +287,26 @@ class Context:
                                           _ptr(planes), float(threshold), _ptr(counts), _stream()))
         return counts
 
+    def count_peaks_masked(self, planes, mask, threshold, boundary, counts=None):
+        """Peaks above threshold whose pixel and neighbours are observed
+        (mask: uint8 ny x nx, non-zero = observed)."""
+        nplanes, ny, nx = int(planes.shape[0]), int(planes.shape[-2]), int(planes.shape[-1])
+        if counts is None:
+            counts = torch.empty(nplanes, dtype=torch.int64, device=planes.device)
+        _check(load().amap_count_peaks_masked(self._h, _dt(planes), ny, nx, nplanes, int(boundary),
+                                              _ptr(planes), _ptr(mask), float(threshold), _ptr(counts),
+                                              _stream()))
+        return counts
+
+    def mask_shear(self, g1, g2, mask, out1=None, out2=None):
+        """Shear with missing pixels zeroed; returns (g1_out, g2_out)."""
+        ny, nx = int(g1.shape[-2]), int(g1.shape[-1])
+        out1 = self._empty((ny, nx), g1) if out1 is None else out1
+        out2 = self._empty((ny, nx), g1) if out2 is None else out2
+        _check(load().amap_mask_shear(self._h, _dt(g1), ny, nx, _ptr(mask), _ptr(g1), _ptr(g2),
+                                      _ptr(out1), _ptr(out2), _stream()))
+        return out1, out2
+
     def starlet_reconstruct(self, planes, out=None):
         J, n = planes.shape[0], _side(planes)
         out = self._empty((n, n), planes) if out is None else out
@@ -403,6 +425,11 @@ class BatchPlan:
 
     def run(self):
         _check(load().amap_batch_run(self._h, _stream()))
+
+    def run_on(self, stream):
+        """Run on an explicit HIP stream handle (None: the null stream,
+        kernels launched directly without a graph)."""
+        _check(load().amap_batch_run(self._h, stream))
 
     def close(self):
         if self._h:

@@ -192,10 +192,17 @@ template <typename T>
 hipError_t launch_welford_bc(const T* w, long long w_stride, int nb, double* M, double* M2,
                              long long count, int r0, hipStream_t s);
 // Peaks above thr of nplanes ny x nx planes under an edge rule (counts:
-// nplanes long long, overwritten).
+// nplanes long long, overwritten); with a mask (NULL: none) only peaks whose
+// pixel and in-field neighbours are observed.
 template <typename T>
-hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes, double thr,
-                                 long long* counts, hipStream_t s);
+hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes,
+                                 const unsigned char* mask, double thr, long long* counts,
+                                 hipStream_t s);
+// Shear of a masked field (count pixels; mask bytes non-zero = observed;
+// outputs may be the inputs).
+template <typename T>
+hipError_t launch_mask_shear(long long count, const T* g1, const T* g2, const unsigned char* mask,
+                             T* o1, T* o2, hipStream_t s);
 template <typename T>
 hipError_t launch_sigma_snr_bc(const double* M2, int R, const T* w_signal, T* sigma, T* snr,
                                long long count, hipStream_t s);

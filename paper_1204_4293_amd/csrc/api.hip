@@ -843,9 +843,9 @@ amap_status amap_ks_invert_padded(amap_ctx_t c, amap_dtype dt, int ny, int nx, i
     return AMAP_OK;
 }
 
-amap_status amap_count_peaks_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int nplanes,
-                                int boundary, const void* planes, double threshold,
-                                long long* counts_dev, void* stream) {
+static amap_status count_peaks_bc_impl(amap_ctx_t c, amap_dtype dt, int ny, int nx, int nplanes,
+                                       int boundary, const void* planes, const unsigned char* mask,
+                                       double threshold, long long* counts_dev, void* stream) {
     g_last_error.clear();
     if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
     AMAP_TRY(check_dtype(dt));
@@ -857,16 +857,69 @@ amap_status amap_count_peaks_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int
         return fail(AMAP_E_INVAL, "boundary must be AMAP_BC_PERIODIC, _MIRROR or _ZERO (got %d)", boundary);
     AMAP_TRY(check_ptr(planes, "planes"));
     AMAP_TRY(check_ptr(counts_dev, "counts_dev"));
+    AMAP_TRY(check_ptr(mask, "mask", false));
     DeviceGuard g(c->device);
     if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
     TimerScope ts(c);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dt == AMAP_F32)
-        AMAP_HIP(launch_count_peaks_bc<float>(ny, nx, nplanes, boundary, (const float*)planes, threshold,
-                                              counts_dev, s), "peak kernel");
+        AMAP_HIP(launch_count_peaks_bc<float>(ny, nx, nplanes, boundary, (const float*)planes, mask,
+                                              threshold, counts_dev, s), "peak kernel");
     else
-        AMAP_HIP(launch_count_peaks_bc<double>(ny, nx, nplanes, boundary, (const double*)planes,
+        AMAP_HIP(launch_count_peaks_bc<double>(ny, nx, nplanes, boundary, (const double*)planes, mask,
                                                threshold, counts_dev, s), "peak kernel");
+    return AMAP_OK;
+}
+
+amap_status amap_count_peaks_bc(amap_ctx_t c, amap_dtype dt, int ny, int nx, int nplanes,
+                                int boundary, const void* planes, double threshold,
+                                long long* counts_dev, void* stream) {
+    return count_peaks_bc_impl(c, dt, ny, nx, nplanes, boundary, planes, nullptr, threshold,
+                               counts_dev, stream);
+}
+
+amap_status amap_count_peaks_masked(amap_ctx_t c, amap_dtype dt, int ny, int nx, int nplanes,
+                                    int boundary, const void* planes, const unsigned char* mask,
+                                    double threshold, long long* counts_dev, void* stream) {
+    if (!mask) {
+        g_last_error.clear();
+        return fail(AMAP_E_INVAL, "mask must not be NULL");
+    }
+    return count_peaks_bc_impl(c, dt, ny, nx, nplanes, boundary, planes, mask, threshold,
+                               counts_dev, stream);
+}
+
+amap_status amap_mask_shear(amap_ctx_t c, amap_dtype dt, int ny, int nx, const unsigned char* mask,
+                            const void* g1, const void* g2, void* g1_out, void* g2_out,
+                            void* stream) {
+    g_last_error.clear();
+    if (!c) return fail(AMAP_E_INVAL, "ctx must not be NULL");
+    AMAP_TRY(check_dtype(dt));
+    if (ny < 1 || nx < 1 || ny > 16384 || nx > 16384)
+        return fail(AMAP_E_INVAL, "field sides must be in [1, 16384] (got %d x %d)", ny, nx);
+    AMAP_TRY(check_ptr(mask, "mask"));
+    AMAP_TRY(check_ptr(g1, "g1"));
+    AMAP_TRY(check_ptr(g2, "g2"));
+    AMAP_TRY(check_ptr(g1_out, "g1_out"));
+    AMAP_TRY(check_ptr(g2_out, "g2_out"));
+    const long long cnt = (long long)ny * nx;
+    const size_t plane = (size_t)cnt * esize(dt);
+    // each output is its own input or apart from every other buffer
+    if ((g1_out != g1 && (overlaps(g1_out, plane, g1, plane) || overlaps(g1_out, plane, g2, plane))) ||
+        (g2_out != g2 && (overlaps(g2_out, plane, g1, plane) || overlaps(g2_out, plane, g2, plane))) ||
+        overlaps(g1_out, plane, g2_out, plane) || overlaps(g1_out, plane, mask, (size_t)cnt) ||
+        overlaps(g2_out, plane, mask, (size_t)cnt))
+        return fail(AMAP_E_INVAL, "each output must be its own input or overlap nothing");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(AMAP_E_HIP, "cannot select device %d", c->device);
+    TimerScope ts(c);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dt == AMAP_F32)
+        AMAP_HIP(launch_mask_shear<float>(cnt, (const float*)g1, (const float*)g2, mask, (float*)g1_out,
+                                          (float*)g2_out, s), "mask kernel");
+    else
+        AMAP_HIP(launch_mask_shear<double>(cnt, (const double*)g1, (const double*)g2, mask,
+                                           (double*)g1_out, (double*)g2_out, s), "mask kernel");
     return AMAP_OK;
 }
 
@@ -1322,23 +1375,42 @@ struct PlanChunk {
     char* base[4];               // g1, g2, kappa, planes of the chunk's first map
 };
 
+// Lanes of a plan: lane 0 runs the grouped chunks, lanes 1.. the jobs that
+// run alone (those with noise, or shapes without grouped kernels), each lane
+// in order on its own workspace region.  In a captured graph the lanes are
+// branches forked from and joined back into the caller's stream, so jobs of
+// different lanes overlap on the device.
+constexpr int kPlanLanes = 4;                  // lanes for jobs that run alone
+constexpr size_t kPlanLaneBytes = 16ull << 30;  // more lanes only within this much workspace
+
 struct amap_plan {
     amap_ctx* ctx = nullptr;
     amap_dtype dt = AMAP_F32;
     std::vector<amap_job> jobs;
     std::vector<PlanChunk> chunks;
     std::vector<int> singles;    // indices of jobs run one at a time
+    std::vector<int> lane_of;    // lane (1..) of each entry of singles
+    std::vector<size_t> lane_off;  // workspace offset of each lane (lane 0: chunks)
+    int lanes = 1;
     void* tabs = nullptr;        // device: per chunk [g1 | g2 | kappa | planes] x count offsets
     Workspace ws;
     hipStream_t graph_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> branch;  // lanes 1.. while capturing (default priority)
+    std::vector<hipEvent_t> ev;       // fork event, then one join event per lane
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         graph_stream = nullptr;
+    }
+    void drop_streams() {
+        for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        branch.clear();
+        ev.clear();
     }
 };
 
@@ -1380,14 +1452,50 @@ static amap_status enqueue_chunk(const amap_plan* p, const PlanChunk& ch, hipStr
     return AMAP_OK;
 }
 
-static amap_status enqueue_plan(amap_plan* p, hipStream_t s) {
+// Every lane's work in lane order on its stream: lanes[l] (lanes[0] = s).
+static amap_status enqueue_lanes(amap_plan* p, const hipStream_t* lanes) {
     for (const PlanChunk& ch : p->chunks)
-        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_chunk<float>(p, ch, s) : enqueue_chunk<double>(p, ch, s));
+        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_chunk<float>(p, ch, lanes[0])
+                                   : enqueue_chunk<double>(p, ch, lanes[0]));
     char* w = static_cast<char*>(p->ws.ptr);
-    for (int i : p->singles) {
-        const amap_job& j = p->jobs[i];
-        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_job<float>(p->ctx, w, j, s)
-                                   : enqueue_job<double>(p->ctx, w, j, s));
+    for (size_t k = 0; k < p->singles.size(); ++k) {
+        const amap_job& j = p->jobs[p->singles[k]];
+        const int l = p->lane_of[k];
+        char* wl = w + p->lane_off[l];
+        AMAP_TRY(p->dt == AMAP_F32 ? enqueue_job<float>(p->ctx, wl, j, lanes[l])
+                                   : enqueue_job<double>(p->ctx, wl, j, lanes[l]));
+    }
+    return AMAP_OK;
+}
+
+// All of the plan on stream s, lane after lane (the lanes' workspace
+// regions are disjoint, so one stream gives the same results).
+static amap_status enqueue_plan(amap_plan* p, hipStream_t s) {
+    std::vector<hipStream_t> lanes(p->lanes, s);
+    return enqueue_lanes(p, lanes.data());
+}
+
+// The plan as branches of the stream being captured: fork every lane from
+// s, join them all back into s.
+static amap_status enqueue_plan_forked(amap_plan* p, hipStream_t s) {
+    if (p->lanes == 1) return enqueue_plan(p, s);
+    if (p->branch.empty()) {
+        p->branch.assign(p->lanes - 1, nullptr);
+        p->ev.assign(p->lanes, nullptr);
+        for (hipStream_t& b : p->branch)
+            AMAP_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "lane stream");
+        for (hipEvent_t& e : p->ev) AMAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "lane event");
+    }
+    std::vector<hipStream_t> lanes(p->lanes, s);
+    AMAP_HIP(hipEventRecord(p->ev[0], s), "fork");
+    for (int l = 1; l < p->lanes; ++l) {
+        lanes[l] = p->branch[l - 1];
+        AMAP_HIP(hipStreamWaitEvent(lanes[l], p->ev[0], 0), "fork wait");
+    }
+    AMAP_TRY(enqueue_lanes(p, lanes.data()));
+    for (int l = 1; l < p->lanes; ++l) {
+        AMAP_HIP(hipEventRecord(p->ev[l], lanes[l]), "join");
+        AMAP_HIP(hipStreamWaitEvent(s, p->ev[l], 0), "join wait");
     }
     return AMAP_OK;
 }
@@ -1428,7 +1536,6 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
         else p->singles.push_back(i);
     }
     size_t need = 0, tab_bytes = 0;
-    for (int i : p->singles) need = std::max(need, job_workspace_bytes(dt, jobs[i]));
     for (auto& kv : groups) {
         const int n = kv.first.first, J = kv.first.second;
         const size_t per = chunk_workspace_bytes(dt, n, 1);
@@ -1441,6 +1548,28 @@ amap_status amap_batch_plan(amap_ctx_t c, amap_dtype dt, const amap_job* jobs, i
             need = std::max(need, chunk_workspace_bytes(dt, n, cnt));
         }
     }
+    // lanes for the jobs that run alone: each job to the lane with the
+    // least work so far (work ~ pixels x (1 + realisations)), as many lanes
+    // as the workspace bound allows (one at least)
+    size_t single_max = 0;
+    for (int i : p->singles) single_max = std::max(single_max, job_workspace_bytes(dt, jobs[i]));
+    int nl = std::min<int>(kPlanLanes, (int)p->singles.size());
+    while (nl > 1 && need + (size_t)nl * single_max > kPlanLaneBytes) --nl;
+    p->lanes = 1 + std::max(nl, p->singles.empty() ? 0 : 1);
+    std::vector<double> load(p->lanes, 0.0);
+    std::vector<size_t> lane_need(p->lanes, 0);
+    lane_need[0] = need;
+    for (int i : p->singles) {
+        int best = 1;
+        for (int l = 2; l < p->lanes; ++l)
+            if (load[l] < load[best]) best = l;
+        load[best] += (double)jobs[i].n * jobs[i].n * (1.0 + jobs[i].n_real);
+        lane_need[best] = std::max(lane_need[best], job_workspace_bytes(dt, jobs[i]));
+        p->lane_of.push_back(best);
+    }
+    p->lane_off.assign(p->lanes, 0);
+    for (int l = 1; l < p->lanes; ++l) p->lane_off[l] = p->lane_off[l - 1] + align256(lane_need[l - 1]);
+    need = p->lane_off[p->lanes - 1] + lane_need[p->lanes - 1];
     amap_status st = p->ws.reserve(need);
     if (st == AMAP_OK && tab_bytes) {
         std::vector<long long> host(tab_bytes / sizeof(long long), 0);
@@ -1503,7 +1632,7 @@ amap_status amap_batch_run(amap_plan_t p, void* stream) {
     if (!p->exec || p->graph_stream != s) {
         p->drop_graph();
         AMAP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-        amap_status st = enqueue_plan(p, s);
+        amap_status st = enqueue_plan_forked(p, s);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(s, &graph);
         if (st != AMAP_OK) {
@@ -1529,6 +1658,7 @@ amap_status amap_plan_destroy(amap_plan_t p) {
     DeviceGuard g(p->ctx->device);
     (void)hipDeviceSynchronize();
     p->drop_graph();
+    p->drop_streams();
     if (p->tabs) (void)hipFree(p->tabs);
     p->ws.release();
     delete p;

@@ -89,6 +89,63 @@ k_bc_col(const T* __restrict__ r, const T* c_prev, T* __restrict__ w, T* c_next,
     c_next[o] = cn;
 }
 
+// One smoothing step at dilation d as a tile: kBcTW consecutive columns by
+// kBcTH rows of one residue class ry (mod d) of the rows, y = ry + d (M0 + m).
+// Taps of the column pass then stay in the class (the edge rule maps each
+// tap row on its own, so the tile simply loads the mapped rows), and the
+// tile stages kBcTH + 4 rows of kBcTW + 4d columns of c_{j-1} once: the row
+// pass runs in LDS on all of them, the column pass on the kBcTH middle rows,
+// and w_j = c_{j-1} - c_j and c_j are written (c_j to a buffer apart from
+// c_{j-1}, whose halo other tiles still read).  grid (column tiles,
+// d * row-tile count, maps); dynamic LDS (kBcTH + 4)(kBcTW + 4d + kBcTW) T,
+// under 64 KiB up to dilation bc_max_d.
+constexpr int kBcTW = 64, kBcTH = 16;
+template <typename T>
+constexpr int bc_max_d() { return sizeof(T) == 4 ? 128 : 64; }
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bc_scale_tile(const T* __restrict__ c_prev, T* __restrict__ w, T* __restrict__ c_next, int ny,
+                int nx, int d, int mode, int row_tiles, long long cp_stride, long long cn_stride,
+                long long w_stride) {
+    extern __shared__ unsigned char lds_raw[];
+    T* reg = reinterpret_cast<T*>(lds_raw);            // [kBcTH + 4][RW]
+    const int RW = kBcTW + 4 * d;
+    T* rr = reg + (kBcTH + 4) * RW;                    // [kBcTH + 4][kBcTW]
+    const int x0 = blockIdx.x * kBcTW;
+    const int ry = blockIdx.y % d, M0 = (blockIdx.y / d) * kBcTH;
+    c_prev += blockIdx.z * cp_stride;
+    c_next += blockIdx.z * cn_stride;
+    w += blockIdx.z * w_stride;
+    // stage: region row m is c_{j-1} row bc(ry + d (M0 + m - 2)), region
+    // column i is column bc(x0 - 2d + i)
+    for (int e = threadIdx.x; e < (kBcTH + 4) * RW; e += 256) {
+        const int m = e / RW, i = e - m * RW;
+        const int yy = bc_index(ry + d * (M0 + m - 2), ny, mode);
+        const int xx = bc_index(x0 - 2 * d + i, nx, mode);
+        reg[e] = (yy < 0 || xx < 0) ? (T)0 : c_prev[(long long)yy * nx + xx];
+    }
+    __syncthreads();
+    // row pass on every staged row
+    for (int e = threadIdx.x; e < (kBcTH + 4) * kBcTW; e += 256) {
+        const int m = e / kBcTW, i = e - m * kBcTW;
+        const T* g = reg + m * RW + i;
+        rr[e] = b3(g[0], g[d], g[2 * d], g[3 * d], g[4 * d]);
+    }
+    __syncthreads();
+    // column pass on the middle rows
+    for (int e = threadIdx.x; e < kBcTH * kBcTW; e += 256) {
+        const int m = e / kBcTW, i = e - m * kBcTW;
+        const int y = ry + d * (M0 + m), x = x0 + i;
+        if (y >= ny || x >= nx) continue;
+        const T* g = rr + m * kBcTW + i;
+        const T cn = b3(g[0], g[kBcTW], g[2 * kBcTW], g[3 * kBcTW], g[4 * kBcTW]);
+        const T cp = reg[(m + 2) * RW + 2 * d + i];
+        const long long o = (long long)y * nx + x;
+        w[o] = cp - cn;
+        c_next[o] = cn;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_pad2(const T* __restrict__ g1, const T* __restrict__ g2, int ny, int nx, int P, T* __restrict__ p1,
@@ -188,11 +245,13 @@ k_sigma_snr_bc(const double* __restrict__ M2, int R, const T* __restrict__ w_sig
 // Strict 8-neighbour maxima above thr of ny x nx planes, neighbours taken
 // through the edge rule (0 outside under the zero rule); grid (blocks,
 // nplanes) of 1024 threads, each block taking rows of its plane in turn,
-// its count gathered in LDS and added once.
+// its count gathered in LDS and added once.  With a mask (bytes, non-zero
+// = observed) a maximum counts only where its pixel and every neighbour
+// inside the field are observed.
 template <typename T>
 __global__ void __launch_bounds__(1024)
-k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double thr,
-                 long long* __restrict__ counts) {
+k_count_peaks_bc(const T* __restrict__ planes, const unsigned char* __restrict__ mask, int ny,
+                 int nx, int mode, double thr, long long* __restrict__ counts) {
     __shared__ unsigned int block_count;
     if (threadIdx.x == 0) block_count = 0u;
     const long long npix = (long long)ny * nx;
@@ -202,7 +261,7 @@ k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double 
         for (int x = threadIdx.x; x < nx; x += 1024) {
             const T v = p[(long long)y * nx + x];
             if (!((double)v > thr)) continue;
-            bool pk = true;
+            bool pk = !mask || mask[(long long)y * nx + x] != 0;
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
                 const int yy = bc_index(y + dy, ny, mode);
@@ -210,8 +269,10 @@ k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double 
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (dy == 0 && dx == 0) continue;
                     const int xx = bc_index(x + dx, nx, mode);
-                    const T q = (yy < 0 || xx < 0) ? (T)0 : p[(long long)yy * nx + xx];
+                    const bool in = yy >= 0 && xx >= 0;
+                    const T q = in ? p[(long long)yy * nx + xx] : (T)0;
                     pk = pk && (v > q);
+                    if (mask && in) pk = pk && mask[(long long)yy * nx + xx] != 0;
                 }
             }
             npk += pk ? 1u : 0u;
@@ -224,43 +285,117 @@ k_count_peaks_bc(const T* __restrict__ planes, int ny, int nx, int mode, double 
         atomicAdd((unsigned long long*)&counts[blockIdx.y], (unsigned long long)block_count);
 }
 
+// Shear of a masked field: both components kept where the mask byte is
+// non-zero and zeroed where the pixel is missing; four pixels per thread
+// (count a multiple of 4, buffers 256-byte aligned), in place allowed.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_mask_shear(const T* g1, const T* g2, const unsigned char* __restrict__ mask, T* o1, T* o2,
+             long long quads) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= quads) return;
+    const uchar4 m = reinterpret_cast<const uchar4*>(mask)[i];
+    const unsigned char mm[4] = {m.x, m.y, m.z, m.w};
+    T a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { a[k] = g1[4 * i + k]; b[k] = g2[4 * i + k]; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        o1[4 * i + k] = mm[k] ? a[k] : (T)0;
+        o2[4 * i + k] = mm[k] ? b[k] : (T)0;
+    }
+}
+
+// The last count % 4 pixels.
+template <typename T>
+__global__ void k_mask_shear_tail(const T* g1, const T* g2, const unsigned char* __restrict__ mask,
+                                  T* o1, T* o2, long long first, long long count) {
+    const long long i = first + threadIdx.x;
+    if (i >= count) return;
+    const T a = g1[i], b = g2[i];
+    o1[i] = mask[i] ? a : (T)0;
+    o2[i] = mask[i] ? b : (T)0;
+}
+
 }  // namespace
 
 template <typename T>
-hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes, double thr,
-                                 long long* counts, hipStream_t s) {
+hipError_t launch_count_peaks_bc(int ny, int nx, int nplanes, int mode, const T* planes,
+                                 const unsigned char* mask, double thr, long long* counts,
+                                 hipStream_t s) {
     hipError_t e = launch_zero_i64(counts, nplanes, s);
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)(ny < 256 ? ny : 256);  // at most 256 adds per counter
     AMAP_LAUNCH("count_peaks_bc", s,
-                k_count_peaks_bc<T><<<dim3(blocks, nplanes), 1024, 0, s>>>(planes, ny, nx, mode, thr, counts));
+                k_count_peaks_bc<T><<<dim3(blocks, nplanes), 1024, 0, s>>>(planes, mask, ny, nx, mode,
+                                                                          thr, counts));
     return hipGetLastError();
 }
-template hipError_t launch_count_peaks_bc<float>(int, int, int, int, const float*, double, long long*,
-                                                 hipStream_t);
-template hipError_t launch_count_peaks_bc<double>(int, int, int, int, const double*, double, long long*,
-                                                  hipStream_t);
+template hipError_t launch_count_peaks_bc<float>(int, int, int, int, const float*, const unsigned char*,
+                                                 double, long long*, hipStream_t);
+template hipError_t launch_count_peaks_bc<double>(int, int, int, int, const double*, const unsigned char*,
+                                                  double, long long*, hipStream_t);
+
+template <typename T>
+hipError_t launch_mask_shear(long long count, const T* g1, const T* g2, const unsigned char* mask,
+                             T* o1, T* o2, hipStream_t s) {
+    const long long quads = count / 4;
+    if (quads > 0)
+        AMAP_LAUNCH("mask_shear", s,
+                    k_mask_shear<T><<<(unsigned)((quads + 255) / 256), 256, 0, s>>>(g1, g2, mask, o1, o2,
+                                                                                   quads));
+    if (count % 4)
+        AMAP_LAUNCH("mask_shear", s,
+                    k_mask_shear_tail<T><<<1, 4, 0, s>>>(g1, g2, mask, o1, o2, 4 * quads, count));
+    return hipGetLastError();
+}
+template hipError_t launch_mask_shear<float>(long long, const float*, const float*, const unsigned char*,
+                                             float*, float*, hipStream_t);
+template hipError_t launch_mask_shear<double>(long long, const double*, const double*,
+                                              const unsigned char*, double*, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T* planes, T* tmp,
                              int maps, long long image_stride, long long planes_stride, hipStream_t s) {
     const long long plane = (long long)ny * nx;
     T* coarse = planes + (long long)(J - 1) * plane;
-    const dim3 grid((nx + 255) / 256, ny, maps);
-    for (int j = 1; j < J; ++j) {
+    // scales 1 .. jt (dilation <= bc_max_d) run as tiles, alternating their
+    // c_j between tmp and the coarse plane so that c_jt lands in the coarse
+    // plane; the later scales run a row and a column pass in place there
+    int jt = 0;
+    while (jt + 1 < J && (1 << jt) <= bc_max_d<T>()) ++jt;
+    const T* c_prev = image;
+    long long cp_stride = image_stride;
+    for (int j = 1; j <= jt; ++j) {
         const int d = 1 << (j - 1);
-        const T* c_prev = j == 1 ? image : coarse;
-        const long long cp_stride = j == 1 ? image_stride : planes_stride;
+        const bool to_coarse = ((jt - j) & 1) == 0;
+        T* dst = to_coarse ? coarse : tmp;
+        const long long dst_stride = to_coarse ? planes_stride : plane;
+        const int rows = (ny + d - 1) / d;  // rows of the largest residue class
+        const int row_tiles = (rows + kBcTH - 1) / kBcTH;
+        const dim3 grid((nx + kBcTW - 1) / kBcTW, d * row_tiles, maps);
+        const size_t lds = (size_t)(kBcTH + 4) * (kBcTW + 4 * d + kBcTW) * sizeof(T);
+        AMAP_LAUNCH("starlet_bc_tile", s,
+                    k_bc_scale_tile<T><<<grid, 256, lds, s>>>(c_prev, planes + (long long)(j - 1) * plane,
+                                                              dst, ny, nx, d, mode, row_tiles, cp_stride,
+                                                              dst_stride, planes_stride));
+        c_prev = dst;
+        cp_stride = dst_stride;
+    }
+    const dim3 grid((nx + 255) / 256, ny, maps);
+    for (int j = jt + 1; j < J; ++j) {
+        const int d = 1 << (j - 1);
         AMAP_LAUNCH("starlet_bc_row", s,
                     k_bc_row<T><<<grid, 256, 0, s>>>(c_prev, tmp, nx, d, mode, cp_stride, plane));
         AMAP_LAUNCH("starlet_bc_col", s,
                     k_bc_col<T><<<grid, 256, 0, s>>>(tmp, c_prev, planes + (long long)(j - 1) * plane,
                                                      coarse, ny, nx, d, mode, plane, cp_stride,
                                                      planes_stride));
+        c_prev = coarse;
+        cp_stride = planes_stride;
     }
     return hipGetLastError();
 }
-
 template <typename T>
 hipError_t launch_pad2(const T* g1, const T* g2, int ny, int nx, int P, T* p1, T* p2, hipStream_t s) {
     AMAP_LAUNCH("pad", s, k_pad2<T><<<dim3((P + 255) / 256, P), 256, 0, s>>>(g1, g2, ny, nx, P, p1, p2));

@@ -124,6 +124,63 @@ def test_plan_with_noise_job_matches_run_path(ctx):
     plan.close()
 
 
+def noise_job(n, J, R, seed, s1, s2, dtype=torch.float32):
+    _, g1, g2 = S.shear_map(n, s1, s2)
+    return {"g1": dev(g1, dtype), "g2": dev(g2, dtype), "n_real": R, "seed": seed, "threshold": 2.0,
+            "planes": torch.empty((J, n, n), dtype=dtype, device="cuda"),
+            "sigma": torch.empty((J - 1, n, n), dtype=dtype, device="cuda"),
+            "snr": torch.empty((J - 1, n, n), dtype=dtype, device="cuda"),
+            "peaks": torch.zeros(J - 1, dtype=torch.int64, device="cuda")}
+
+
+def test_plan_noise_jobs_as_graph_branches(ctx):
+    # noise jobs of a plan run on up to four lanes, forked from and joined
+    # back into the caller's stream inside the captured graph; every replay
+    # (eager work and synchronisations between them, outputs poisoned before
+    # each) equals run_path job by job, and the grouped maps still match
+    # the oracle
+    specs = [(64, 4, 5, 11), (128, 5, 9, 12), (256, 6, 4, 13), (128, 5, 3, 14), (64, 3, 6, 15),
+             (512, 7, 4, 16), (32, 3, 2, 17)]
+    njobs = [noise_job(n, J, R, seed, 400 + k, 600 + k) for k, (n, J, R, seed) in enumerate(specs)]
+    gjobs, refs = make_jobs([64, 128, 128, 256], torch.float32, 700, lambda i: i % 2 == 0)
+    refs_path = []
+    for (n, J, R, seed), j in zip(specs, njobs):
+        refs_path.append(ctx.run_path(j["g1"], j["g2"], J, R, seed, 2.0))
+    torch.cuda.synchronize()
+    plan = amap.BatchPlan(ctx, gjobs[:2] + njobs[:4] + gjobs[2:] + njobs[4:])
+    side = torch.cuda.Stream()
+    scratch = torch.zeros((256, 256), device="cuda")
+    for replay in range(4):
+        for j in njobs:
+            for key in ("planes", "sigma", "snr"):
+                j[key].fill_(float("nan"))
+            j["peaks"].fill_(-1)
+        for j in gjobs:
+            j["planes"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            plan.run()
+        side.synchronize()
+        for k, (j, ref) in enumerate(zip(njobs, refs_path)):
+            for key in ("planes", "sigma", "snr", "peaks"):
+                assert torch.equal(j[key], ref[key]), (replay, k, key)
+        for (g1, g2, J), job in zip(refs, gjobs):
+            kE, _ = O.ks_invert(g1, g2)
+            assert maxerr(host(job["planes"]), O.starlet_forward(kE, J)) <= 1e-5 * rms(kE)
+        # eager work of the program's own between replays
+        ctx.ks_invert(njobs[2]["g1"], njobs[2]["g2"], kappa_e=scratch)
+        scratch.mul_(2.0)
+        torch.cuda.synchronize()
+    # the direct path (null stream) runs the lanes one after another
+    for j in njobs:
+        j["sigma"].fill_(float("nan"))
+    plan.run_on(None)
+    torch.cuda.synchronize()
+    for j, ref in zip(njobs, refs_path):
+        assert torch.equal(j["sigma"], ref["sigma"])
+    plan.close()
+
+
 def test_uneven_batch_sampled_against_oracle(ctx):
     # the uneven-batch size distribution (sides 128..2048, weights 4:4:3:2:1),
     # first 40 draws; per-map seeds 1000 + i; J = log2 N - 2
