@@ -14,10 +14,12 @@ Printed as one JSON line.  Extra objects:
   batched      512 uneven maps (KS + starlet) as one grouped, graph-captured
                plan, and the same maps one launch sequence per map
   served       a Poisson request stream through the library's request loop:
-               saturated rate, then p50/p99 latency at 0.5 and 0.8 of it
+               saturated rate, then p50/p99 latency at 0.25, 0.5 and 0.8 of it
   statistics   plane moments and peak-height histograms on the step's planes
   direct_vs_starlet  map_direct at theta = 2..64 (cut theta) vs KS + starlet
                with J = log2 theta + 1 on the 1024^2 map (the paper's comparison)
+  small_fp64   one 256^2 float64 map: KS + starlet J = 5 latency, and map_direct
+               at theta = 2, 4, 8
   bounded      a 1000 x 1000 field with edges (a crop of the map): KS of the
                field zero-extended into a 2048^2 grid + starlet J = 7 under the
                mirror edge rule; and its noise sigma, S/N and peaks from 16
@@ -699,6 +701,38 @@ def main():
         direct["theta_%d" % theta] = {"J": Jt, "map_direct_ms": t_dir, "ks_starlet_ms": t_sw,
                                       "speedup": t_dir / t_sw}
 
+    # the small double-precision case: one 256^2 FP64 map (GRF seed 1, shape
+    # noise seed 2), KS + starlet J = 5 per call, and map_direct at theta =
+    # 2, 4, 8 (cut theta), latency per map on an idle GPU
+    _, s1, s2 = synth.shear_map(256, 1, 2)
+    d1 = torch.tensor(s1, dtype=torch.float64, device=dev)
+    d2 = torch.tensor(s2, dtype=torch.float64, device=dev)
+    dke = torch.empty((256, 256), dtype=torch.float64, device=dev)
+    dpl = torch.empty((5, 256, 256), dtype=torch.float64, device=dev)
+    ddm = torch.empty((256, 256), dtype=torch.float64, device=dev)
+
+    def small_once():
+        ctx.ks_invert(d1, d2, kappa_e=dke)
+        ctx.starlet_forward(dke, 5, planes=dpl)
+    small_once()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(50):
+        small_once()
+    ev1.record()
+    torch.cuda.synchronize()
+    small = {"workload": "256x256 float64 map (GRF seed 1, noise seed 2), KS + starlet J=5",
+             "ms_per_map": ev0.elapsed_time(ev1) / 50, "map_direct_ms": {}}
+    for theta in (2, 4, 8):
+        ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=ddm)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(20):
+            ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=ddm)
+        ev1.record()
+        torch.cuda.synchronize()
+        small["map_direct_ms"]["theta_%d" % theta] = ev0.elapsed_time(ev1) / 20
+
     # statistics of the step's planes: central moments of the J planes and
     # the peak-height histogram of the S/N planes, 20 calls each
     mom = torch.empty((J, 4), dtype=torch.float64, device=dev)
@@ -784,6 +818,7 @@ def main():
                                / (HBM_PEAK_GBS * 1e9),
         "plain": plain, "batched": batched, "served": served, "statistics": stats,
         "direct_vs_starlet": direct,
+        "small_fp64": small,
         "bounded": bounded,
         "roofline": roofline,
         "step": step,

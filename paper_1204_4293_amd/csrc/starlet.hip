@@ -107,6 +107,16 @@ __device__ __forceinline__ VArr<T, G> vcombine(const VArr<T, G>& a0, const VArr<
     return r;
 }
 
+// Whether the passes can be laid out as a grid over NT threads (as
+// tile_scale_pass_grid does) for a tile TXT values wide and a stage of ns
+// scales: a tile row's vectors, padded to a multiple of eight, fit the
+// threads, and the row groups that leaves cover the dilation 2^(ns-1) of the
+// stage's last column pass (its window chains go to row groups in
+// multiples of the dilation).
+__host__ __device__ constexpr bool grid_fits(int TXT, int G, int NT, int ns) {
+    return ((TXT / G + 7) & ~7) <= NT && NT / ((TXT / G + 7) & ~7) >= (1 << (ns - 1));
+}
+
 // Geometry shared by the host planner and the kernel: the x halo is rounded
 // up to whole vectors so the output tile starts on a vector boundary; each
 // LDS row has one vector of padding on either side (read only by outputs
@@ -471,7 +481,9 @@ __device__ __forceinline__ void store_owned(T* dst, const TileGeom& g,
     }
 }
 
-// Write mode: maps in gridDim.y; stores w_j and the stage's last c.
+// Write mode: maps in gridDim.y; stores w_j and the stage's last c.  The
+// planes are written once and not read again here, so they go out with
+// non-temporal stores.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
@@ -508,7 +520,7 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
                 VA wv;
 #pragma unroll
                 for (int cc = 0; cc < G; ++cc) wv.e[cc] = prev[k].e[cc] - c.e[cc];
-                vstore<T, G>(wp + owned_global(g, p * G), wv);
+                vstore_stream<T, G>(wp + owned_global(g, p * G), wv);
                 prev[k] = c;
             }
         }
@@ -1088,7 +1100,7 @@ static int stage_candidates(int n, int j0, int ns, bool noise, StageGeom* out, i
                 if (sizeof(T) == 8 && cfg.nt > 512) continue;  // no 1024-thread double stages
                 if (cfg.kv > 1 && ns == 3) continue;  // three scales of state for 4 vectors would spill
                 if ((TXT / G) * TVT > cfg.nt * noise_prefetch(cfg.nt, cfg.kv)) continue;
-                if (((TXT / G + 7) & ~7) > cfg.nt) continue;  // a tile row's vectors spread over the threads
+                if (!grid_fits(TXT, G, cfg.nt, ns)) continue;  // a tile row's vectors spread over the threads
             }
             insert(StageGeom{ns, nt, tw, th, lds, 1}, r);
             if (noise && sizeof(T) == 4 && ns <= 2) {
@@ -1179,7 +1191,7 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
         const int d0 = 1 << (a.j0 - 1);
         const int TXT = g.tw + 2 * stage_hx(d0, NS, G), TVT = g.th + 2 * 2 * ((1 << NS) - 1);
         if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV, RB) || g.tw * g.th > NT * KV * G ||
-            ((TXT / G + 7) & ~7) > NT ||
+            !grid_fits(TXT, G, NT, NS) ||
             g.lds < (size_t)(2 * RB * (TXT + 2 * G) * TVT + G) * sizeof(T))
             return hipErrorInvalidConfiguration;
     }
