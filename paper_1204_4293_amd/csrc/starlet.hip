@@ -489,19 +489,32 @@ __global__ void __launch_bounds__(NT) k_starlet_stage(StageArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const TileGeom g = tile_geom(a.logn, a.j0, a.ns, a.log_tw, a.th, G);
     const long long n2 = (long long)g.n * g.n;
     T* A = reinterpret_cast<T*>(smem_raw) + G;  // element (v, i) at A[v*RS + i], i in [-G, TXT+G)
     T* Bf = A + g.RS * g.TVT;
     const int map = blockIdx.y;
     const T* src = a.src + (a.src_off ? a.src_off[map] : (long long)map * a.src_stride);
-    const int tvec = g.TXT / G;
-    for (int v = wave; v < g.TVT; v += NW) {
-        const long long row = tile_row(g, v);
-        for (int c = lane; c < tvec; c += 64)
-            vstore<T, G>(A + v * g.RS + c * G, vload<T, G>(src + row + ((g.x0 - g.Hx + c * G) & g.m)));
+    // the tile (with its halo) into LDS: every thread's vectors at a stride
+    // of NT over the tile, four loads in flight before their stores
+    const int tvec = g.TXT / G, nload = g.TVT * tvec;
+    const float inv_tvec = 1.0f / (float)tvec;
+    for (int e0 = threadIdx.x; e0 < nload; e0 += 4 * NT) {
+        VA r[4];
+        int off[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = e0 + k * NT;
+            off[k] = -1;
+            if (e < nload) {
+                const int v = fdiv(e, inv_tvec), c = e - v * tvec;
+                r[k] = vload<T, G>(src + tile_row(g, v) + ((g.x0 - g.Hx + c * G) & g.m));
+                off[k] = v * g.RS + c * G;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (off[k] >= 0) vstore<T, G>(A + off[k], r[k]);
     }
     lds_barrier();
     VA prev[kVecPerThread];
