@@ -16,10 +16,11 @@ Printed as one JSON line.  Extra objects:
   served       a Poisson request stream through the library's request loop:
                saturated rate, then p50/p99 latency at 0.25, 0.5 and 0.8 of it
   statistics   plane moments and peak-height histograms on the step's planes
-  direct_vs_starlet  map_direct at theta = 2..64 (cut theta) vs KS + starlet
-               with J = log2 theta + 1 on the 1024^2 map (the paper's comparison)
+  direct_vs_starlet  map_direct at theta = 2..64 (cut theta, and cut 2 theta)
+               vs KS + starlet with J = log2 theta + 1 on the 1024^2 map (the
+               paper's comparison)
   small_fp64   one 256^2 float64 map: KS + starlet J = 5 latency, and map_direct
-               at theta = 2, 4, 8
+               at theta = 2, 4, 8 (cut 2 theta)
   bounded      a 1000 x 1000 field with edges (a crop of the map): KS of the
                field zero-extended into a 2048^2 grid + starlet J = 7 under the
                mirror edge rule; and its noise sigma, S/N and peaks from 16
@@ -698,12 +699,24 @@ def main():
         ev1.record()
         torch.cuda.synchronize()
         t_sw = ev0.elapsed_time(ev1) / 20
+        # the filter's natural support (cut = 2 theta for the starlet Q)
+        ctx.map_direct(t1, t2, float(theta), amap.FILTER_STARLET, 0.0, 0.0, out=dm)
+        torch.cuda.synchronize()
+        reps2 = 3 if theta >= 32 else 20
+        ev0.record()
+        for _ in range(reps2):
+            ctx.map_direct(t1, t2, float(theta), amap.FILTER_STARLET, 0.0, 0.0, out=dm)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_dir2 = ev0.elapsed_time(ev1) / reps2
         direct["theta_%d" % theta] = {"J": Jt, "map_direct_ms": t_dir, "ks_starlet_ms": t_sw,
-                                      "speedup": t_dir / t_sw}
+                                      "speedup": t_dir / t_sw, "map_direct_cut_2theta_ms": t_dir2,
+                                      "speedup_cut_2theta": t_dir2 / t_sw}
 
     # the small double-precision case: one 256^2 FP64 map (GRF seed 1, shape
     # noise seed 2), KS + starlet J = 5 per call, and map_direct at theta =
-    # 2, 4, 8 (cut theta), latency per map on an idle GPU
+    # 2, 4, 8 (the starlet Q's natural support, cut = 2 theta), latency per
+    # map on an idle GPU
     _, s1, s2 = synth.shear_map(256, 1, 2)
     d1 = torch.tensor(s1, dtype=torch.float64, device=dev)
     d2 = torch.tensor(s2, dtype=torch.float64, device=dev)
@@ -724,11 +737,11 @@ def main():
     small = {"workload": "256x256 float64 map (GRF seed 1, noise seed 2), KS + starlet J=5",
              "ms_per_map": ev0.elapsed_time(ev1) / 50, "map_direct_ms": {}}
     for theta in (2, 4, 8):
-        ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=ddm)
+        ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, 0.0, out=ddm)
         torch.cuda.synchronize()
         ev0.record()
         for _ in range(20):
-            ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, float(theta), out=ddm)
+            ctx.map_direct(d1, d2, float(theta), amap.FILTER_STARLET, 0.0, 0.0, out=ddm)
         ev1.record()
         torch.cuda.synchronize()
         small["map_direct_ms"]["theta_%d" % theta] = ev0.elapsed_time(ev1) / 20

@@ -465,7 +465,11 @@ amap_status amap_server_create(amap_ctx_t ctx, amap_dtype dt, size_t mem_budget,
  * everything enqueued on `stream` before the call (for instance the work
  * that produced its inputs or initialised its outputs), whatever slot it is
  * admitted to.  AMAP_E_NOMEM if its footprint alone exceeds the budget
- * (never admissible); AMAP_E_BUSY if max_queued jobs already wait. */
+ * (never admissible); AMAP_E_BUSY if max_queued jobs already wait.  A job
+ * whose starlet shape has no tile schedule in the context yet (with
+ * autotuning on) is tuned when it is admitted, which blocks the admitting
+ * call until the job's submit point has been reached on the device and the
+ * timing runs are done; amap_plans_load beforehand avoids that. */
 amap_status amap_server_submit(amap_server_t srv, const amap_job* job, void* stream,
                                long long* ticket);
 
