@@ -49,8 +49,6 @@ def field(ny, nx, seed):
 @pytest.mark.parametrize("rule", RULES)
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_bounded_starlet_matches_oracle(ctx, ny, nx, J, rule, dtype):
-    if dtype == torch.float64 and ny * nx > 300000:
-        pytest.skip("FP64 checked on the smaller fields")
     print("bounded starlet %dx%d J=%d rule=%d %s" % (ny, nx, J, rule, dtype), flush=True)
     a = field(ny, nx, 40 + ny + nx)
     got = ctx.starlet_forward_bc(dev(a, dtype), J, rule)
@@ -76,8 +74,6 @@ def test_bounded_periodic_square_agrees_with_the_tiled_transform(ctx):
                                      (1, 300, 512)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_padded_ks_matches_oracle(ctx, ny, nx, P, dtype):
-    if dtype == torch.float64 and P > 512:
-        pytest.skip("FP64 checked on the smaller grids")
     print("padded KS %dx%d P=%d %s" % (ny, nx, P, dtype), flush=True)
     n = 16
     while n < max(ny, nx):
