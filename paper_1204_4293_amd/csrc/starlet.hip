@@ -338,19 +338,28 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
 // (nrg of them) step down rows [0, nrows) of the pass, so a thread's items
 // lie at a fixed stride from its first one at `off`; every item is done for
 // each of the RB tiles (tstride apart).
+// DXC > 0: the five taps lie in three vectors (dilation DXC <= G / 2);
+// DXC = 0: five vector loads at the dilation dx.
 template <typename T, int RB, int DXC>
 __device__ __forceinline__ void row_pass_grid(const T* A, T* Bf, int off, int r, int nrows, int nrg,
                                               int RS, int dx, int tstride) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
     const int step = nrg * RS;
-    for (; r < nrows; r += nrg, off += step) {
+    // per tile the item's offset, moved by one step per item; the reads are
+    // addressed from the leftmost tap vector, so every tap is a non-negative
+    // constant offset from one base
+    const int lead = DXC > 0 ? G : 2 * dx;
+    int ro[RB];  // element offsets (kept as integers: the pointers stay in LDS)
+#pragma unroll
+    for (int t = 0; t < RB; ++t) ro[t] = t * tstride + off;
+    for (; r < nrows; r += nrg) {
         VA o[RB];
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
-            const T* ra = A + t * tstride + off;
-            if constexpr (DXC != 0) {
-                const VA l = vload<T, G>(ra - G), c = vload<T, G>(ra), rr = vload<T, G>(ra + G);
+            const T* ra = A + (ro[t] - lead);
+            if constexpr (DXC > 0) {
+                const VA l = vload<T, G>(ra), c = vload<T, G>(ra + G), rr = vload<T, G>(ra + 2 * G);
                 T w[3 * G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) { w[k] = l.e[k]; w[G + k] = c.e[k]; w[2 * G + k] = rr.e[k]; }
@@ -360,12 +369,15 @@ __device__ __forceinline__ void row_pass_grid(const T* A, T* Bf, int off, int r,
                     o[t].e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
                 }
             } else {
-                o[t] = vcombine<T, G>(vload<T, G>(ra - 2 * dx), vload<T, G>(ra - dx), vload<T, G>(ra),
-                                      vload<T, G>(ra + dx), vload<T, G>(ra + 2 * dx));
+                o[t] = vcombine<T, G>(vload<T, G>(ra), vload<T, G>(ra + dx), vload<T, G>(ra + 2 * dx),
+                                      vload<T, G>(ra + 3 * dx), vload<T, G>(ra + 4 * dx));
             }
         }
 #pragma unroll
-        for (int t = 0; t < RB; ++t) vstore<T, G>(Bf + t * tstride + off, o[t]);
+        for (int t = 0; t < RB; ++t) {
+            vstore<T, G>(Bf + ro[t], o[t]);
+            ro[t] += step;
+        }
     }
 }
 
@@ -700,6 +712,10 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
             for (int k = 0; k < KV; ++k)
                 if (owner[k]) prev[t][k] = vload<T, G>(A + t * tstride + owned_lds(g, own_e[k]));
         int xlo = 0, xhi = g.TXT, vlo = 0, vhi = g.TVT;
+        // Welford weights 1 / (number of realisations so far), once per round
+        AccT inv[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) inv[t] = (AccT)1 / (AccT)(i0 + t + 1);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {  // unrolled: the Welford state keeps static indices
             // three scales of sums leave no registers for a second row item
@@ -708,7 +724,6 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
                 if (i0 + t >= count) continue;
-                const AccT inv = (AccT)1 / (AccT)(i0 + t + 1);
 #pragma unroll
                 for (int k = 0; k < KV; ++k) {
                     if (!owner[k]) continue;
@@ -717,7 +732,7 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                     for (int cc = 0; cc < G; ++cc) {
                         const AccT x = (AccT)(prev[t][k].e[cc] - c.e[cc]);
                         const AccT d = x - mean[s][k][cc];
-                        mean[s][k][cc] = fma(d, inv, mean[s][k][cc]);
+                        mean[s][k][cc] = fma(d, inv[t], mean[s][k][cc]);
                         m2[s][k][cc] = fma(d, x - mean[s][k][cc], m2[s][k][cc]);
                     }
                     prev[t][k] = c;
@@ -863,6 +878,10 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
         for (int k = PD - RB; k < PD; ++k) pf[k] = fetch(i0 + k + RB);
 #pragma unroll
         for (int t = 0; t < RB; ++t) vstore<T, G>(A + t * TS + own, prev[t]);
+        // Welford weights 1 / (number of realisations so far), once per round
+        AccT inv[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) inv[t] = (AccT)1 / (AccT)(i0 + t + 1);
         __syncthreads();  // A complete; every read of B by the previous pass done
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -893,7 +912,6 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
             }
             __syncthreads();  // B complete
             // realisations in order, so the Welford sequence matches one at a time
-            const AccT inv_base = (AccT)(i0 + 1);
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
                 const T* cb = B + t * TS + xo;
@@ -903,12 +921,11 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
                                             vload<T, G>(cb + ((yo + d) & (M - 1)) * RS),
                                             vload<T, G>(cb + ((yo + 2 * d) & (M - 1)) * RS));
                 if (RB == 1 || i0 + t < count) {
-                    const AccT inv = (AccT)1 / (inv_base + (AccT)t);
 #pragma unroll
                     for (int cc = 0; cc < G; ++cc) {
                         const AccT x = (AccT)(prev[t].e[cc] - c.e[cc]);
                         const AccT dd = x - mean[s][cc];
-                        mean[s][cc] = fma(dd, inv, mean[s][cc]);
+                        mean[s][cc] = fma(dd, inv[t], mean[s][cc]);
                         m2[s][cc] = fma(dd, x - mean[s][cc], m2[s][cc]);
                     }
                 }
