@@ -100,9 +100,10 @@ size_t amap_workspace_bytes(amap_ctx_t ctx);
 /* Tile autotuning (on by default).  The first starlet transform of each
  * shape (element type, n, J, signal or noise statistics, batch) on a stream
  * that is not being captured times the candidate LDS tiles of every stage
- * start and scale count on the call's own buffers and keeps, per context,
- * the schedule of least total time (dynamic programming over the stage
- * starts); later calls of that shape reuse it.  Batch plans tune at
+ * start and scale count on the call's own buffers (for noise statistics
+ * also stages on sub-grid images and final sub-grid stages) and keeps, per
+ * context, the schedule of least total time (dynamic programming over the
+ * stage starts); later calls of that shape reuse it.  Batch plans tune at
  * creation with one direct run of the plan.  Results do not depend on the
  * schedule except, for noise statistics, in the rounding of how per-group
  * partial statistics are merged.  enable = 0 uses the analytic planner
@@ -117,10 +118,16 @@ amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
  * the NUL): [{"mode": 1 (tuned) | 2 (analytic with sub-grid final stage, see
  * amap_set_autotune), "elem": bytes per value, "logn", "J", "noise": 0|1, "batch",
  * "stages": [[j0, ns, tile width, tile sub-rows, realisations per LDS
- * pass, sub-grid stage 0|1], ...]}, ...]; a sub-grid stage is a final noise
- * stage on whole periodic sub-grids of 2^(j0-1) (width and sub-rows are the
- * sub-grid side); an empty
- * stage list means the analytic planner is used for that shape.
+ * pass, kind], ...]}, ...].  Every scale from j0 on couples only pixels
+ * congruent mod d = 2^(j0-1) (the a-trous dilations, Sec. 2.3), so the d^2
+ * sub-grids of such pixels are independent periodic images of side n / d.
+ * kind 0: an LDS tile stage; kind 1 (noise statistics, the last stage): a
+ * final stage on whole sub-grids, one per workgroup (width and sub-rows are
+ * the sub-grid side); kind 2 (noise statistics): a tile stage on the
+ * sub-grids of d taken as images, with the tile of an (n/d) x (n/d) map's
+ * first stage; it follows a kind-0 stage and is the last stage or followed
+ * by a kind-1 stage.  An empty stage list means the analytic planner is
+ * used for that shape.
  * AMAP_E_INVAL if it does not fit. */
 amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);
 

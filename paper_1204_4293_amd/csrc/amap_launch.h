@@ -70,14 +70,34 @@ template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 // 3*batch*n*n, the detail planes of one stage.
 // A starlet stage schedule: stage k covers scales st[k].j0 .. j0+ns-1 with
 // an LDS tile of tw pixels by th sub-rows, rb realisations per LDS pass
-// (noise stages; 1 otherwise); sub = 1 marks a final noise stage on whole
-// sub-grids of d0 = 2^(j0-1) (tw = th = n / d0), whose input and running
-// statistics are in sub-grid order.  nstages == 0: use the analytic planner.
+// (noise stages; 1 otherwise).  kind (noise stages only):
+//   kStageSubgrid: a final stage on whole sub-grids of d0 = 2^(j0-1)
+//     (tw = th = n / d0), whose input and running statistics are in
+//     sub-grid order;
+//   kStageImages: a tile stage on the sub-grids of d0 = 2^(j0-1) taken as
+//     periodic images of side n / d0 (its scales start at dilation 1 there;
+//     tw, th a tile of such an image), whose input and running statistics
+//     are in that sub-grid order; it follows a plain tile stage and is the
+//     last stage or followed by the final sub-grid stage, whose sub-grids it
+//     lays out image by image.
+// nstages == 0: use the analytic planner.
+enum { kStageTile = 0, kStageSubgrid = 1, kStageImages = 2 };
 struct StagePlan {
     int nstages = 0;
-    struct Stage { int j0, ns, tw, th, rb, sub; } st[16];
+    struct Stage { int j0, ns, tw, th, rb, kind; } st[16];
+    // a one-stage noise plan (timed by the tuner) writes its coarse output
+    // in sub-grid order for d = 2^cout_logd, as before a sub-grid stage
+    int cout_logd = 0;
     // first scale whose running statistics are in sub-grid order (0: none)
-    int subgrid_j0() const { return nstages > 0 && st[nstages - 1].sub ? st[nstages - 1].j0 : 0; }
+    int subgrid_j0() const {
+        return nstages > 0 && st[nstages - 1].kind == kStageSubgrid ? st[nstages - 1].j0 : 0;
+    }
+    // first scale of the stage on sub-grid images (0: none)
+    int images_j0() const {
+        for (int k = 0; k < nstages; ++k)
+            if (st[k].kind == kStageImages) return st[k].j0;
+        return 0;
+    }
 };
 
 template <typename T>
@@ -133,7 +153,7 @@ hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStrea
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s,
-                                 int subgrid_j0 = 0);
+                                 int subgrid_j0 = 0, int images_j0 = 0);
 hipError_t launch_zero_f64(double* p, long long count, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long count, hipStream_t s);
 

@@ -402,7 +402,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
         AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
     AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s,
-                                      plan ? plan->subgrid_j0() : 0),
+                                      plan ? plan->subgrid_j0() : 0, plan ? plan->images_j0() : 0),
              "noise finalize");
     return AMAP_OK;
 }
@@ -555,7 +555,7 @@ amap_status amap_plans_load(amap_ctx_t c, const char* json) {
         e.mode = (int)v[0];
         e.key = {(int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]};
         e.plan.nstages = 0;
-        // stages: [[j0, ns, tw, th, rb, sub], ...] up to the closing bracket
+        // stages: [[j0, ns, tw, th, rb, kind], ...] up to the closing bracket
         while (true) {
             while (*st == ' ' || *st == ',') ++st;
             if (*st == ']') { ++st; break; }
@@ -605,7 +605,7 @@ amap_status amap_plans_read(amap_ctx_t c, char* buf, size_t len) {
             out += item;
             for (int k = 0; k < kv.second.nstages; ++k) {
                 const StagePlan::Stage& t = kv.second.st[k];
-                snprintf(item, sizeof item, "%s[%d, %d, %d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th, t.rb, t.sub);
+                snprintf(item, sizeof item, "%s[%d, %d, %d, %d, %d, %d]", k ? ", " : "", t.j0, t.ns, t.tw, t.th, t.rb, t.kind);
                 out += item;
             }
             out += "]}";

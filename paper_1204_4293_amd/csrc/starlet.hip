@@ -161,10 +161,15 @@ __device__ __forceinline__ void lds_barrier() {
 // Geometry of one tile of a stage, shared by the write and noise kernels.
 struct TileGeom {
     int n, m, d0, Hx, Hv, TXT, TVT, RS, tw, log_tw, th, x0, v0, q, nvec;
+    long long base;  // offset of the tile's image in the plane
 };
 
+// The tile of this workgroup in a plane that holds 4^logi periodic images
+// of side 2^logn one after another (logi = 0: the plane is one image; a
+// plane in sub-grid order for d = 2^logi holds its d^2 sub-grids so),
+// the stage starting at scale j0 of each image.
 __device__ __forceinline__ TileGeom tile_geom(int logn, int j0, int ns, int log_tw, int th,
-                                              int G) {
+                                              int G, int logi = 0) {
     TileGeom g;
     g.n = 1 << logn; g.m = g.n - 1;
     g.tw = 1 << log_tw; g.log_tw = log_tw; g.th = th;
@@ -173,12 +178,19 @@ __device__ __forceinline__ TileGeom tile_geom(int logn, int j0, int ns, int log_
     g.Hv = 2 * ((1 << ns) - 1);
     g.TXT = g.tw + 2 * g.Hx; g.TVT = th + 2 * g.Hv;
     g.RS = g.TXT + 2 * G;
-    // tile index: x-tiles fastest, then sub-row tiles, then the row residue;
-    // consecutive tiles (which share halos) are kept on one XCD
+    // tile index: x-tiles fastest, then sub-row tiles, then the row residue,
+    // then the image; consecutive tiles (which share halos) are kept on one XCD
     const int ntx = g.n >> log_tw, ntv = (g.n / g.d0) / th;
     const int ntiles = ntx * ntv * g.d0;
+    const int total = ntiles << (2 * logi);
     int t = blockIdx.x;
-    if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    if ((total & 7) == 0) t = (t & 7) * (total >> 3) + (t >> 3);
+    g.base = 0;
+    if (logi > 0) {
+        const int img = t / ntiles;
+        t -= img * ntiles;
+        g.base = (long long)img << (2 * logn);
+    }
     const int xt = t % ntx, vt = (t / ntx) % ntv;
     g.q = t / (ntx * ntv);
     g.x0 = xt * g.tw; g.v0 = vt * th;
@@ -186,12 +198,12 @@ __device__ __forceinline__ TileGeom tile_geom(int logn, int j0, int ns, int log_
     return g;
 }
 
-// Global row of tile row v, and global pixel row of owned output row pv.
+// Offset of tile row v in the plane, and of owned output row pv.
 __device__ __forceinline__ long long tile_row(const TileGeom& g, int v) {
-    return (long long)((g.q + g.d0 * (g.v0 - g.Hv + v)) & g.m) * g.n;
+    return g.base + (long long)((g.q + g.d0 * (g.v0 - g.Hv + v)) & g.m) * g.n;
 }
 __device__ __forceinline__ long long out_row(const TileGeom& g, int pv) {
-    return (long long)((g.q + g.d0 * (g.v0 + pv)) & g.m) * g.n;
+    return g.base + (long long)((g.q + g.d0 * (g.v0 + pv)) & g.m) * g.n;
 }
 
 // Splits e into (e / d, e % d) with a float reciprocal; exact for e < 16384
@@ -573,7 +585,10 @@ struct NoiseStageArgs {
     double* M2;
     void* part;              // [groups][ns][2][n^2] partials (accumulator type) when groups > 1
     float inv_tvec;          // 1 / (vectors per tile row), for index splitting
-    int cout_logd = 0;       // > 0: cout in sub-grid order for d = 2^cout_logd (subgrid_index)
+    int cout_logd = 0;       // > 0: cout in sub-grid order for d = 2^cout_logd (subgrid_index),
+                             // within each image
+    int img_logd = 0;        // > 0: src, cout, M and M2 hold the d^2 sub-grids of d = 2^img_logd
+                             // (subgrid_index) as periodic images, each transformed on its own
 };
 
 // Single-precision one-vector stages of 256 or 512 threads keep to 128
@@ -588,8 +603,10 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
     constexpr int G = Vec<T>::G;
     using VA = VArr<T, G>;
     using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
-    const TileGeom g = tile_geom(a.logn, a.j0, NS, a.log_tw, a.th, G);
-    const long long n2 = (long long)g.n * g.n;
+    // on sub-grid images, scale j0 is the image's scale j0 - img_logd
+    const int logm = a.logn - a.img_logd;
+    const TileGeom g = tile_geom(logm, a.j0 - a.img_logd, NS, a.log_tw, a.th, G, a.img_logd);
+    const long long n2 = 1ll << (2 * a.logn);
     // RB realisations at a time, tile t in [A_t | B_t], A_t = A + t * tstride
     const int tstride = 2 * g.RS * g.TVT;
     T* A = reinterpret_cast<T*>(smem_raw) + G;
@@ -633,8 +650,9 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
     // the coarse values a round hands on are stored during the next round,
     // before its loads are issued: waiting for a round's loads then never
     // waits for stores issued after them.  Three-scale and four-vector
-    // stages have no registers to spare and store at once.
-    constexpr bool DEFER = NS < 3 && KV == 1;
+    // stages have no registers to spare and store at once, and so do stages
+    // whose output goes out in sub-grid order (its addresses would spill).
+    constexpr bool DEFER = NS < 3 && KV == 1 && !SG;
     VA keep[RB][KV];
     // Sub-grid order of the coarse output (for d = 2^cout_logd): where the
     // tile width is a multiple of G d, a tile row holds, per sub-grid
@@ -668,11 +686,13 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
                 } else if (sg_vec) {
                     int pv, xr;
                     sg_pos(own_e[k], pv, xr);
-                    vstore_stream<T, G>(dst + subgrid_index(out_row(g, pv) + g.x0 + xr, a.logn, a.cout_logd),
+                    vstore_stream<T, G>(dst + g.base + subgrid_index(out_row(g, pv) - g.base + g.x0 + xr,
+                                                                     logm, a.cout_logd),
                                         keep[t][k]);
                 } else {
 #pragma unroll
-                    for (int c = 0; c < G; ++c) dst[subgrid_index(gi + c, a.logn, a.cout_logd)] = keep[t][k].e[c];
+                    for (int c = 0; c < G; ++c)
+                        dst[g.base + subgrid_index(gi - g.base + c, logm, a.cout_logd)] = keep[t][k].e[c];
                 }
             }
         }
@@ -1215,10 +1235,11 @@ static hipError_t launch_noise_stage_nt(const NoiseStageArgs<T>& a, const StageG
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if (a.cout_logd < 0 || a.cout_logd >= a.logn) return hipErrorInvalidValue;
+    if (a.img_logd < 0 || a.img_logd >= a.j0 || a.cout_logd < 0 || a.cout_logd >= a.logn - a.img_logd)
+        return hipErrorInvalidValue;
     {  // the tile must fit the prefetch registers and the owned vectors of the threads
         constexpr int G = Vec<T>::G;
-        const int d0 = 1 << (a.j0 - 1);
+        const int d0 = 1 << (a.j0 - 1 - a.img_logd);
         const int TXT = g.tw + 2 * stage_hx(d0, NS, G), TVT = g.th + 2 * 2 * ((1 << NS) - 1);
         if ((TXT / G) * TVT > NT * noise_prefetch(NT, KV, RB) || g.tw * g.th > NT * KV * G ||
             !grid_fits(TXT, G, NT, NS) ||
@@ -1293,6 +1314,15 @@ static bool subgrid_ok(int n, int j0, int J) {
     if (d0 > n / 16) return false;
     const int m = n / d0;
     return m >= 16 && m <= (sizeof(T) == 4 ? 64 : 32);
+}
+
+// A noise tile stage on the sub-grids of d0 = 2^(j0-1) as periodic images
+// of side m = n / d0: the geometry of the tile (tw, th, rb) of an m x m
+// map's first stage of ns scales.  False if the planner offers no such tile.
+template <typename T>
+static bool images_geom(int n, int j0, int ns, int tw, int th, int rb, StageGeom* g) {
+    if (j0 < 2 || ns < 1 || ns > 3 || (n >> (j0 - 1)) < 16) return false;
+    return stage_geom_of<T>(n >> (j0 - 1), 1, ns, tw, th, rb, true, g);
 }
 
 // LDS of a sub-grid stage: RB tiles of m rows of m values, twice.
@@ -1438,13 +1468,22 @@ bool plan_valid(int n, int J, bool noise, const StagePlan& plan) {
     for (int k = 0; k < plan.nstages; ++k) {
         const StagePlan::Stage& t = plan.st[k];
         if (t.j0 != j || t.ns < 1 || t.j0 + t.ns > J) return false;
-        if (t.sub) {
+        if (t.kind == kStageSubgrid) {
             if (!noise || k + 1 != plan.nstages || t.j0 + t.ns != J || !subgrid_ok<T>(n, t.j0, J) ||
                 (t.rb != 1 && t.rb != 2) || t.tw != (n >> (t.j0 - 1)) || t.th != t.tw)
                 return false;
-        } else {
+        } else if (t.kind == kStageImages) {
+            // after a plain tile stage; the last stage or followed by the final sub-grid stage
+            StageGeom g{};
+            if (!noise || k == 0 || plan.st[k - 1].kind != kStageTile ||
+                (k + 1 < plan.nstages && plan.st[k + 1].kind != kStageSubgrid) || t.ns > 3 ||
+                !images_geom<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, &g))
+                return false;
+        } else if (t.kind == kStageTile) {
             StageGeom g{};
             if (t.ns > 3 || !stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, noise, &g)) return false;
+        } else {
+            return false;
         }
         j += t.ns;
     }
@@ -1462,7 +1501,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
     const long long n2 = (long long)n * n;
     const bool acc = a.M != nullptr;
     // plan the stages: (j0, ns, tile) or a per-scale stage (tile.nt == 0)
-    struct Stage { int j0, ns; StageGeom g; bool tiled, sub; };
+    struct Stage { int j0, ns; StageGeom g; bool tiled, sub, images; };
     Stage plan[16];
     int nstages = 0;
     if (a.plan && a.plan->nstages > 0) {
@@ -1470,23 +1509,32 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         for (int k = 0; k < a.plan->nstages; ++k) {
             const StagePlan::Stage& t = a.plan->st[k];
             StageGeom g{};
-            if (t.sub) {  // a final noise stage on whole sub-grids
+            if (t.kind == kStageSubgrid) {  // a final noise stage on whole sub-grids
                 if (!acc || k + 1 != a.plan->nstages || t.j0 + t.ns != a.J || !subgrid_ok<T>(n, t.j0, a.J) ||
                     (t.rb != 1 && t.rb != 2))
                     return hipErrorInvalidValue;
                 g.rb = t.rb;
-                plan[nstages++] = Stage{t.j0, t.ns, g, false, true};
+                plan[nstages++] = Stage{t.j0, t.ns, g, false, true, false};
                 continue;
             }
-            if (!stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, acc, &g)) return hipErrorInvalidValue;
-            plan[nstages++] = Stage{t.j0, t.ns, g, true, false};
+            if (t.kind == kStageImages) {  // noise tiles on sub-grid images
+                if (!acc || (k > 0 && a.plan->st[k - 1].kind != kStageTile) ||
+                    (k + 1 < a.plan->nstages && a.plan->st[k + 1].kind != kStageSubgrid) ||
+                    !images_geom<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, &g))
+                    return hipErrorInvalidValue;
+                plan[nstages++] = Stage{t.j0, t.ns, g, true, false, true};
+                continue;
+            }
+            if (t.kind != kStageTile || !stage_geom_of<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, acc, &g))
+                return hipErrorInvalidValue;
+            plan[nstages++] = Stage{t.j0, t.ns, g, true, false, false};
         }
     } else {
         for (int j0 = 1; j0 < a.J; ) {
             StageGeom g{};
             const bool tiled = pick_stage<T>(n, j0, a.J - j0, acc, &g);
             const int ns = tiled ? g.ns : 1;
-            plan[nstages++] = Stage{j0, ns, g, tiled, false};
+            plan[nstages++] = Stage{j0, ns, g, tiled, false, false};
             j0 += ns;
         }
     }
@@ -1539,6 +1587,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
         int lt = 0;
         while ((1 << lt) < st.g.tw) ++lt;
         if (st.sub) {  // acc only, the last stage: c and the statistics in sub-grid order
+            // (after a stage on sub-grid images, their sub-grids image by image)
             const int d0 = 1 << (st.j0 - 1);
             const int tiles = d0 * d0;
             int logm = 0;
@@ -1567,8 +1616,10 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             continue;
         }
         if (st.tiled && acc) {
-            const int d0 = 1 << (st.j0 - 1);
-            const int tiles = (n / st.g.tw) * ((n / d0) / st.g.th) * d0;
+            // on sub-grid images (of side nm), the stage starts at dilation 1 there
+            const int li = st.images ? st.j0 - 1 : 0;
+            const int d0 = 1 << (st.j0 - 1 - li), nm = n >> li;
+            const int tiles = ((nm / st.g.tw) * ((nm / d0) / st.g.th) * d0) << (2 * li);
             NoiseStageArgs<T> s;
             s.logn = a.logn; s.j0 = st.j0; s.ns = st.ns; s.log_tw = lt; s.th = st.g.th;
             s.src = cur; s.cout = dst; s.batch = a.batch;
@@ -1576,8 +1627,12 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             s.M = a.M + (long long)(st.j0 - 1) * n2; s.M2 = a.M2 + (long long)(st.j0 - 1) * n2;
             s.part = a.part;
             s.inv_tvec = 1.0f / (float)((st.g.tw + 2 * stage_hx(d0, st.ns, Vec<T>::G)) / Vec<T>::G);
-            // a following sub-grid stage reads c in its sub-grid order
-            s.cout_logd = (gi + 1 < nstages && plan[gi + 1].sub) ? plan[gi + 1].j0 - 1 : 0;
+            // a following sub-grid or sub-grid image stage reads c in its
+            // sub-grid order (within each image of this one)
+            s.img_logd = li;
+            s.cout_logd = (gi + 1 < nstages && (plan[gi + 1].sub || plan[gi + 1].images))
+                              ? plan[gi + 1].j0 - 1 - li
+                              : (a.plan && nstages == 1 && !st.images && dst ? a.plan->cout_logd : 0);
             {
                 using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
                 if (s.groups > 1 && (size_t)s.groups * st.ns * 2 * (size_t)n2 * sizeof(AccT) >
@@ -1670,83 +1725,117 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // best[j]: least time for scales j .. J-1; pick[j]: its first stage
-    float best[18];
-    StagePlan::Stage pick[18];
-    best[J] = 0.f;
-    for (int j = J - 1; j >= 1 && e == hipSuccess; --j) {
-        best[j] = -1.f;
-        for (int ns = 1; ns <= 3 && j + ns <= J && e == hipSuccess; ++ns) {
-            if (best[j + ns] < 0.f) continue;
-            // the two best tiles (least halo overhead) of each thread configuration
-            // (threads, owned vectors, realisations per pass)
-            StageGeom all[kMaxCand], cand[24];
-            const int na = stage_candidates<T>(n, j, ns, acc, all, kMaxCand);
-            auto config = [&](const StageGeom& sg) {
-                const NoiseCfg cfg = noise_cfg(sg.tw * sg.th / Vec<T>::G);
-                return acc ? (cfg.nt * 8 + cfg.kv) * 4 + sg.rb : sg.nt;
-            };
-            int nc = 0;
-            for (int i = 0; i < na && nc < 24; ++i) {
-                const int key = config(all[i]);
-                int same = 0;
-                for (int q = 0; q < nc; ++q) same += config(cand[q]) == key;
-                if (same < 2) cand[nc++] = all[i];
-            }
-            for (int c = 0; c < nc && e == hipSuccess; ++c) {
-                StagePlan sub;
-                sub.nstages = 1;
-                sub.st[0] = StagePlan::Stage{j, ns, cand[c].tw, cand[c].th, cand[c].rb, 0};
-                StarletArgs<T> b = a;
-                b.plan = &sub;
-                if (j > 1 && b.planes_off) {  // grouped: later stages read the c buffers
-                    b.kappa = b.cbuf0;
-                    b.kappa_off = nullptr;
-                }
-                e = launch_starlet<T>(b);       // warm
-                if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_starlet<T>(b);
-                if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) break;
-                if (tune_log())
-                    std::fprintf(stderr, "amap tune: n=%d J=%d %s batch=%d stage j0=%d ns=%d tile %dx%d rb=%d: %.1f us\n",
-                                 n, J, acc ? "noise" : "signal", a.batch, j, ns, cand[c].tw,
-                                 cand[c].th, cand[c].rb, 1e3f * ms / reps);
-                const float t = ms / reps + best[j + ns];
-                if (best[j] < 0.f || t < best[j]) {
-                    best[j] = t;
-                    pick[j] = sub.st[0];
-                }
-            }
+    // the average time of one stage alone (reps launches after a warm one)
+    auto time_stage = [&](const StagePlan::Stage& st, float* us, int cout_logd = 0) {
+        StagePlan sub;
+        sub.nstages = 1;
+        sub.st[0] = st;
+        sub.cout_logd = cout_logd;
+        StarletArgs<T> b = a;
+        b.plan = &sub;
+        if (st.j0 > 1 && b.planes_off) {  // grouped: later stages read the c buffers
+            b.kappa = b.cbuf0;
+            b.kappa_off = nullptr;
         }
+        hipError_t r = launch_starlet<T>(b);  // warm
+        if (r == hipSuccess) r = hipEventRecord(e0, a.stream);
+        for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_starlet<T>(b);
+        if (r == hipSuccess) r = hipEventRecord(e1, a.stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        *us = 1e3f * ms / reps;
+        if (r == hipSuccess && tune_log()) {
+            const char* kind = st.kind == kStageSubgrid ? "sub-grids" : st.kind == kStageImages ? "image tile" : "tile";
+            std::fprintf(stderr, "amap tune: n=%d J=%d %s batch=%d stage j0=%d ns=%d %s %dx%d rb=%d: %.1f us\n",
+                         n, J, acc ? "noise" : "signal", a.batch, st.j0, st.ns, kind, st.tw, st.th, st.rb, *us);
+        }
+        return r;
+    };
+    // the two best tiles (least halo overhead) of each thread configuration
+    // (threads, owned vectors, realisations per pass) of a stage of ns
+    // scales from j0 of an m x m map
+    auto candidates = [&](int m, int j0, int ns, StageGeom* cand) {
+        StageGeom all[kMaxCand];
+        const int na = stage_candidates<T>(m, j0, ns, acc, all, kMaxCand);
+        auto config = [&](const StageGeom& sg) {
+            const NoiseCfg cfg = noise_cfg(sg.tw * sg.th / Vec<T>::G);
+            return acc ? (cfg.nt * 8 + cfg.kv) * 4 + sg.rb : sg.nt;
+        };
+        int nc = 0;
+        for (int i = 0; i < na && nc < 24; ++i) {
+            const int key = config(all[i]);
+            int same = 0;
+            for (int q = 0; q < nc; ++q) same += config(cand[q]) == key;
+            if (same < 2) cand[nc++] = all[i];
+        }
+        return nc;
+    };
+    // best[j]: least time for scales j .. J-1 from c_{j-1} in natural order,
+    // pick[j] its first stage, then_images[j] whether a stage on sub-grid
+    // images follows it; img[j]: least time for scales j .. J-1 starting with
+    // a stage on sub-grid images (then the final sub-grid stage, if any
+    // scales are left), img_pick[j] that stage; sub[j]: the final sub-grid
+    // stage from j, sub_pick[j] it.
+    float best[18], img[18], sub[18];
+    StagePlan::Stage pick[18], img_pick[18], sub_pick[18];
+    bool then_images[18];
+    best[J] = 0.f;
+    img[J] = sub[J] = -1.f;
+    for (int j = J - 1; j >= 1 && e == hipSuccess; --j) {
+        best[j] = img[j] = sub[j] = -1.f;
+        then_images[j] = false;
         for (int rb = 1; rb <= 2 && acc && e == hipSuccess && subgrid_ok<T>(n, j, J); ++rb) {
             // all remaining scales on whole sub-grids (a final stage)
             const int m = n >> (j - 1);
-            StagePlan sub;
-            sub.nstages = 1;
-            sub.st[0] = StagePlan::Stage{j, J - j, m, m, rb, 1};
-            StarletArgs<T> b = a;
-            b.plan = &sub;
-            e = launch_starlet<T>(b);  // warm
-            if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_starlet<T>(b);
-            if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess) {
-                if (tune_log())
-                    std::fprintf(stderr, "amap tune: n=%d J=%d noise batch=%d stage j0=%d ns=%d sub-grids %dx%d rb=%d: %.1f us\n",
-                                 n, J, a.batch, j, J - j, m, m, rb, 1e3f * ms / reps);
-                const float t = ms / reps;
-                if (best[j] < 0.f || t < best[j]) {
-                    best[j] = t;
-                    pick[j] = sub.st[0];
+            const StagePlan::Stage st{j, J - j, m, m, rb, kStageSubgrid};
+            float t = 0.f;
+            e = time_stage(st, &t);
+            if (e == hipSuccess && (sub[j] < 0.f || t < sub[j])) {
+                sub[j] = t;
+                sub_pick[j] = st;
+            }
+        }
+        // a tile stage on the sub-grid images of d0 = 2^(j-1)
+        for (int ns = 1; ns <= 3 && acc && j >= 2 && j + ns <= J && (n >> (j - 1)) >= 16 && e == hipSuccess; ++ns) {
+            const float tail = j + ns == J ? 0.f : sub[j + ns];
+            if (tail < 0.f) continue;
+            StageGeom cand[24];
+            const int nc = candidates(n >> (j - 1), 1, ns, cand);
+            for (int c = 0; c < nc && e == hipSuccess; ++c) {
+                const StagePlan::Stage st{j, ns, cand[c].tw, cand[c].th, cand[c].rb, kStageImages};
+                float t = 0.f;
+                e = time_stage(st, &t);
+                if (e == hipSuccess && (img[j] < 0.f || t + tail < img[j])) {
+                    img[j] = t + tail;
+                    img_pick[j] = st;
                 }
             }
+        }
+        for (int ns = 1; ns <= 3 && j + ns <= J && e == hipSuccess; ++ns) {
+            const float rest = best[j + ns], rest_img = img[j + ns];
+            if (rest < 0.f && rest_img < 0.f) continue;
+            const bool via_img = rest_img >= 0.f && (rest < 0.f || rest_img < rest);
+            // before a stage on sub-grids the coarse output goes out in their order
+            const bool to_sub = via_img || (j + ns < J && pick[j + ns].kind == kStageSubgrid);
+            StageGeom cand[24];
+            const int nc = candidates(n, j, ns, cand);
+            for (int c = 0; c < nc && e == hipSuccess; ++c) {
+                const StagePlan::Stage st{j, ns, cand[c].tw, cand[c].th, cand[c].rb, kStageTile};
+                float t = 0.f;
+                e = time_stage(st, &t, acc && to_sub ? j + ns - 1 : 0);
+                const float total = t + (via_img ? rest_img : rest);
+                if (e == hipSuccess && (best[j] < 0.f || total < best[j])) {
+                    best[j] = total;
+                    pick[j] = st;
+                    then_images[j] = via_img;
+                }
+            }
+        }
+        if (sub[j] >= 0.f && (best[j] < 0.f || sub[j] < best[j])) {
+            best[j] = sub[j];
+            pick[j] = sub_pick[j];
+            then_images[j] = false;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -1754,7 +1843,17 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
     if (e != hipSuccess) return e;
     if (best[1] < 0.f) return hipErrorNotSupported;  // some stage start has no tile
     out->nstages = 0;
-    for (int j = 1; j < J; j += pick[j].ns) out->st[out->nstages++] = pick[j];
+    for (int j = 1; j < J;) {
+        const bool to_img = then_images[j];
+        out->st[out->nstages++] = pick[j];
+        j += pick[j].ns;
+        if (to_img) {
+            out->st[out->nstages++] = img_pick[j];
+            j += img_pick[j].ns;
+            if (j < J) out->st[out->nstages++] = sub_pick[j];
+            break;
+        }
+    }
     return hipSuccess;
 }
 template hipError_t tune_starlet<float>(const StarletArgs<float>&, int, StagePlan*);

@@ -1,0 +1,135 @@
+"""Noise tile stages on sub-grid images (stage kind 2 of a schedule).
+
+From scale j0 on, the B3 cascade only couples pixels congruent mod
+d = 2^(j0-1), so the d^2 sub-grids of such pixels are independent periodic
+images of side n / d on which scale j0 + s has dilation 2^s.  A stage of
+kind 2 takes the previous stage's coarse plane in that sub-grid order and
+runs the ordinary noise tile stage on every image: its x halo is that of a
+first stage instead of growing with d.  It is the last stage or is followed
+by the final sub-grid stage, whose sub-grids it lays out image by image; the
+finalize kernel maps each scale's statistics back to pixel order.
+
+Schedules with such stages are loaded explicitly (amap_plans_load, keyed by
+the batch the call runs) and checked against the FP64 oracle: sigma within
+1e-5 * rms(kappa) (1e-10 for float64), against the analytic tile-only
+schedule to rounding, S/N by the propagated bound and peak counts bit-exact
+on identical planes.  Capped batches cover the cross-batch merge of these
+statistics.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle_pool
+import synth as S
+import paper_1204_4293_amd as amap
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-5, torch.float64: 1e-10}
+ELEM = {torch.float32: 4, torch.float64: 8}
+
+# (n, J, R, dtype, batch cap (0: none), stages [j0, ns, tw, th, rb, kind])
+CASES = [
+    (1024, 7, 10, torch.float32, 0, [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 2], [5, 2, 64, 64, 2, 1]]),
+    (256, 6, 9, torch.float32, 4, [[1, 2, 64, 32, 1, 0], [3, 2, 64, 32, 1, 2], [5, 1, 16, 16, 2, 1]]),
+    (256, 5, 6, torch.float32, 0, [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 2]]),
+    (512, 7, 5, torch.float32, 0, [[1, 1, 64, 32, 1, 0], [2, 3, 64, 64, 1, 2], [5, 2, 32, 32, 1, 1]]),
+    (512, 7, 5, torch.float32, 2, [[1, 2, 64, 32, 1, 0], [3, 1, 64, 32, 1, 2], [4, 3, 64, 64, 1, 1]]),
+    (256, 6, 4, torch.float64, 0, [[1, 2, 32, 32, 1, 0], [3, 2, 32, 32, 1, 2], [5, 1, 16, 16, 1, 1]]),
+    (128, 5, 5, torch.float64, 2, [[1, 1, 32, 16, 1, 0], [2, 2, 32, 16, 1, 2], [4, 1, 16, 16, 1, 1]]),
+]
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rms(a):
+    return float(np.sqrt(np.mean(np.asarray(a, dtype=np.float64) ** 2)))
+
+
+def schedule(n, J, R, dtype, cap, stages):
+    batch = cap if cap else amap.noise_batch(n, R)
+    return {"mode": 1, "elem": ELEM[dtype], "logn": n.bit_length() - 1, "J": J, "noise": 1,
+            "batch": batch, "stages": stages}
+
+
+def context(cap, autotune=True):
+    c = amap.Context(0)
+    c.set_autotune(autotune)
+    if cap:
+        c.set_noise_batch(cap)
+    return c
+
+
+@pytest.mark.parametrize("n,J,R,dtype,cap,stages", CASES)
+def test_image_stage_sigma_against_oracle_and_tiles(n, J, R, dtype, cap, stages):
+    print("image stages n=%d J=%d R=%d %s cap=%d %s" % (n, J, R, dtype, cap, stages), flush=True)
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    ctx, tile = context(cap), context(cap, autotune=False)
+    plan = schedule(n, J, R, dtype, cap, stages)
+    ctx.plans_load([plan])
+    seed = 300 + n + J + R
+    _, g1, g2 = S.shear_map(n, 60 + n, 61 + J)
+    t1, t2 = dev(g1, dtype), dev(g2, dtype)
+    sa, _ = ctx.noise_maps(t1, t2, J, R, seed, want_snr=False)
+    sb, _ = tile.noise_maps(t1, t2, J, R, seed, want_snr=False)
+    torch.cuda.synchronize()
+    # the loaded schedule is the only one: nothing was tuned beside it
+    assert ctx.plans() == [plan]
+    a, b = sa.double().cpu().numpy(), sb.double().cpu().numpy()
+    assert float(np.abs(a - b).max()) <= (1e-6 if dtype == torch.float32 else 1e-12) * float(np.abs(b).max())
+    kE, _ = O.ks_invert(g1, g2)
+    ref = oracle_pool.noise_sigma_pool(g1, g2, J, R, seed)
+    assert float(np.abs(a - ref).max()) <= TOL[dtype] * rms(kE)
+    ctx.close()
+    tile.close()
+
+
+def test_image_stage_path_snr_and_peaks():
+    n, J, R, seed, thr = 256, 6, 7, 44, 2.0
+    ctx = context(0)
+    ctx.plans_load([schedule(n, J, R, torch.float32, 0,
+                             [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 2], [5, 1, 16, 16, 2, 1]])])
+    _, g1, g2 = S.shear_map(n, 71, 72)
+    out = ctx.run_path(dev(g1, torch.float32), dev(g2, torch.float32), J, R, seed, thr)
+    torch.cuda.synchronize()
+    kE, _ = O.ks_invert(g1, g2)
+    sig_ref = O.noise_sigma(g1, g2, J, R, seed)
+    snr_ref = O.snr_planes(O.starlet_forward(kE, J), sig_ref)
+    tol = 1e-5 * rms(kE)
+    assert float(np.abs(out["sigma"].double().cpu().numpy() - sig_ref).max()) <= tol
+    sn = out["snr"].double().cpu().numpy()
+    assert np.all(np.abs(sn - snr_ref) * sig_ref <= tol * (1.0 + np.abs(snr_ref)) * (1 + 1e-6))
+    assert [int(v) for v in out["peaks"].cpu()] == O.count_peaks_planes(out["snr"].cpu().numpy(), thr)
+    snr32 = snr_ref.astype(np.float32)
+    got = ctx.count_peaks(dev(snr32, torch.float32), thr)
+    assert [int(v) for v in got.cpu()] == O.count_peaks_planes(snr32, thr)
+    ctx.close()
+
+
+def test_image_stage_schedules_are_validated():
+    ctx = context(0)
+    n, J, R = 1024, 7, 10
+    good = [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 2], [5, 2, 64, 64, 2, 1]]
+    bad = [
+        [[1, 2, 64, 32, 2, 2], [3, 2, 64, 32, 2, 0], [5, 2, 64, 64, 2, 1]],   # images stage first
+        [[1, 2, 64, 32, 2, 0], [3, 1, 64, 32, 2, 2], [4, 1, 64, 32, 2, 0], [5, 2, 64, 64, 2, 1]],  # then a tile stage
+        [[1, 2, 64, 32, 2, 0], [3, 1, 64, 32, 2, 2], [4, 1, 64, 32, 2, 2], [5, 2, 64, 64, 2, 1]],  # two in a row
+        [[1, 2, 64, 32, 2, 0], [3, 2, 48, 32, 2, 2], [5, 2, 64, 64, 2, 1]],   # no such tile
+        [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 3], [5, 2, 64, 64, 2, 1]],   # no such kind
+    ]
+    for stages in bad:
+        with pytest.raises(amap.AmapError):
+            ctx.plans_load([schedule(n, J, R, torch.float32, 0, stages)])
+    assert ctx.plans() == []
+    # signal schedules (no noise statistics) take no images stage
+    sig = schedule(n, J, R, torch.float32, 0, good)
+    sig["noise"] = 0
+    with pytest.raises(amap.AmapError):
+        ctx.plans_load([sig])
+    ctx.plans_load([schedule(n, J, R, torch.float32, 0, good)])
+    assert ctx.plans()[0]["stages"] == good
+    ctx.close()
