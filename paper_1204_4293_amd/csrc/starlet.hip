@@ -35,6 +35,18 @@ template <typename T>
 __device__ __forceinline__ T b3_combine(T a0, T a1, T a2, T a3, T a4) {
     return ((a0 + a4) + (T)4 * (a1 + a3) + (T)6 * a2) * (T)0.0625;
 }
+// The tiled passes split the normalisation: a row pass stores 16 times its
+// B3 average (b3_row, no multiply) and the column pass scales its sum of
+// those by 1/256 (b3_col).  Every factor is a power of two, so each value a
+// column pass stores is bit for bit what two normalised passes give.
+template <typename T>
+__device__ __forceinline__ T b3_row(T a0, T a1, T a2, T a3, T a4) {
+    return (a0 + a4) + (T)4 * (a1 + a3) + (T)6 * a2;
+}
+template <typename T>
+__device__ __forceinline__ T b3_col(T a0, T a1, T a2, T a3, T a4) {
+    return ((a0 + a4) + (T)4 * (a1 + a3) + (T)6 * a2) * (T)0.00390625;
+}
 
 constexpr int kLdsBytes = 160 * 1024 - 1024;
 
@@ -98,12 +110,21 @@ __device__ __forceinline__ void vstore_stream(T* p, const VArr<T, G>& r) {
     __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<T>::type*>(p));
 }
 template <typename T, int G>
-__device__ __forceinline__ VArr<T, G> vcombine(const VArr<T, G>& a0, const VArr<T, G>& a1,
-                                               const VArr<T, G>& a2, const VArr<T, G>& a3,
-                                               const VArr<T, G>& a4) {
+__device__ __forceinline__ VArr<T, G> vrow(const VArr<T, G>& a0, const VArr<T, G>& a1,
+                                           const VArr<T, G>& a2, const VArr<T, G>& a3,
+                                           const VArr<T, G>& a4) {
     VArr<T, G> r;
 #pragma unroll
-    for (int c = 0; c < G; ++c) r.e[c] = b3_combine(a0.e[c], a1.e[c], a2.e[c], a3.e[c], a4.e[c]);
+    for (int c = 0; c < G; ++c) r.e[c] = b3_row(a0.e[c], a1.e[c], a2.e[c], a3.e[c], a4.e[c]);
+    return r;
+}
+template <typename T, int G>
+__device__ __forceinline__ VArr<T, G> vcol(const VArr<T, G>& a0, const VArr<T, G>& a1,
+                                           const VArr<T, G>& a2, const VArr<T, G>& a3,
+                                           const VArr<T, G>& a4) {
+    VArr<T, G> r;
+#pragma unroll
+    for (int c = 0; c < G; ++c) r.e[c] = b3_col(a0.e[c], a1.e[c], a2.e[c], a3.e[c], a4.e[c]);
     return r;
 }
 
@@ -239,10 +260,10 @@ __device__ __forceinline__ void row_pass(const T* A, T* Bf, int RS, int dx, int 
 #pragma unroll
             for (int k = 0; k < G; ++k) {
                 const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
-                o.e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
+                o.e[k] = b3_row(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
             }
         } else {
-            o = vcombine<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
+            o = vrow<T, G>(vload<T, G>(ra + i0 - 2 * dx), vload<T, G>(ra + i0 - dx),
                                vload<T, G>(ra + i0), vload<T, G>(ra + i0 + dx),
                                vload<T, G>(ra + i0 + 2 * dx));
         }
@@ -325,7 +346,7 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
             T* op = A + tb + vfirst * RS + i0;
 #pragma unroll
             for (int k = 0; k < kSegLen; ++k)
-                vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+                vstore<T, G>(op + k * step, vcol<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
             continue;
         }
 #pragma unroll
@@ -338,7 +359,7 @@ __device__ __forceinline__ void tile_scale_pass(T* A, T* Bf, const TileGeom& g, 
             const int v = vfirst + dv * k;
             if (v < chi)
                 vstore<T, G>(A + tb + v * RS + i0,
-                             vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+                             vcol<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
         }
     }
     lds_barrier();
@@ -378,10 +399,10 @@ __device__ __forceinline__ void row_pass_grid(const T* A, T* Bf, int off, int r,
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
                     const int b = G + k;  // DXC * 2 <= G keeps every tap inside w
-                    o[t].e[k] = b3_combine(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
+                    o[t].e[k] = b3_row(w[b - 2 * DXC], w[b - DXC], w[b], w[b + DXC], w[b + 2 * DXC]);
                 }
             } else {
-                o[t] = vcombine<T, G>(vload<T, G>(ra), vload<T, G>(ra + dx), vload<T, G>(ra + 2 * dx),
+                o[t] = vrow<T, G>(vload<T, G>(ra), vload<T, G>(ra + dx), vload<T, G>(ra + 2 * dx),
                                       vload<T, G>(ra + 3 * dx), vload<T, G>(ra + 4 * dx));
             }
         }
@@ -452,7 +473,7 @@ __device__ __forceinline__ void tile_scale_pass_grid(T* A, T* Bf, const TileGeom
                 for (int k = 0; k < kSegLen + 4; ++k) win[k] = vload<T, G>(wp + k * step);
 #pragma unroll
                 for (int k = 0; k < kSegLen; ++k)
-                    vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+                    vstore<T, G>(op + k * step, vcol<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
             } else {
 #pragma unroll
                 for (int k = 0; k < kSegLen + 4; ++k)
@@ -460,7 +481,7 @@ __device__ __forceinline__ void tile_scale_pass_grid(T* A, T* Bf, const TileGeom
 #pragma unroll
                 for (int k = 0; k < kSegLen; ++k)
                     if (vfirst + dv * k < chi)
-                        vstore<T, G>(op + k * step, vcombine<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
+                        vstore<T, G>(op + k * step, vcol<T, G>(win[k], win[k + 1], win[k + 2], win[k + 3], win[k + 4]));
             }
         }
     }
@@ -919,12 +940,12 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
 #pragma unroll
                     for (int k = 0; k < G; ++k) {
                         const int b = G + k;
-                        o.e[k] = d == 1 ? b3_combine(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
-                                        : b3_combine(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
+                        o.e[k] = d == 1 ? b3_row(w[b - 2], w[b - 1], w[b], w[b + 1], w[b + 2])
+                                        : b3_row(w[b - 4 > 0 ? b - 4 : 0], w[b - 2], w[b], w[b + 2],
                                                      w[b + 4 < 3 * G ? b + 4 : 3 * G - 1]);
                     }
                 } else {  // the dilation is a multiple of the vector width
-                    o = vcombine<T, G>(vload<T, G>(ra + ((xo - 2 * d) & (M - 1))), vload<T, G>(ra + ((xo - d) & (M - 1))),
+                    o = vrow<T, G>(vload<T, G>(ra + ((xo - 2 * d) & (M - 1))), vload<T, G>(ra + ((xo - d) & (M - 1))),
                                        vload<T, G>(ra + xo), vload<T, G>(ra + ((xo + d) & (M - 1))),
                                        vload<T, G>(ra + ((xo + 2 * d) & (M - 1))));
                 }
@@ -935,7 +956,7 @@ k_starlet_noise_subgrid(NoiseSubArgs<T> a) {
 #pragma unroll
             for (int t = 0; t < RB; ++t) {
                 const T* cb = B + t * TS + xo;
-                const VA c = vcombine<T, G>(vload<T, G>(cb + ((yo - 2 * d) & (M - 1)) * RS),
+                const VA c = vcol<T, G>(vload<T, G>(cb + ((yo - 2 * d) & (M - 1)) * RS),
                                             vload<T, G>(cb + ((yo - d) & (M - 1)) * RS),
                                             vload<T, G>(cb + yo * RS),
                                             vload<T, G>(cb + ((yo + d) & (M - 1)) * RS),
