@@ -889,11 +889,12 @@ template <typename T, int LOGN>
 constexpr bool use_generic() { return sizeof(T) == 8 && LOGN >= 10; }
 
 // Pairs of maps share the inverse transform where the four-step kernels run
-// and the four exchange rows of a unit fit the 64 KiB of static LDS.
+// and the four exchange rows of a unit fit 128 KiB of LDS (as the row pass's
+// four rows do): up to n = 2048 in float32.
 template <typename T, int LOGN>
 constexpr bool pair_ok() {
-    return !use_generic<T, LOGN>() &&
-           (size_t)RowPair<T, LOGN>::UNITS * 4 * Row4<T, LOGN>::EX * sizeof(cpx<T>) <= 65536;
+    return !use_generic<T, LOGN>() && 2 * FS<LOGN>::N2 <= 64 &&
+           (size_t)RowPair<T, LOGN>::UNITS * 4 * Row4<T, LOGN>::EX * sizeof(cpx<T>) <= 128 * 1024;
 }
 
 // The four-step kernels with strips of WREQ columns.
