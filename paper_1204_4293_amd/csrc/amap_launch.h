@@ -77,9 +77,10 @@ template <typename T> hipError_t launch_ks(const KsArgs<T>& a);
 //   kStageImages: a tile stage on the sub-grids of d0 = 2^(j0-1) taken as
 //     periodic images of side n / d0 (its scales start at dilation 1 there;
 //     tw, th a tile of such an image), whose input and running statistics
-//     are in that sub-grid order; it follows a plain tile stage and is the
-//     last stage or followed by the final sub-grid stage, whose sub-grids it
-//     lays out image by image.
+//     are in that sub-grid order; it follows a plain tile stage or another
+//     such stage, and is the last stage or followed by another such stage
+//     or the final sub-grid stage, whose sub-grids it lays out image by
+//     image (nested sub-grid orders).
 // nstages == 0: use the analytic planner.
 enum { kStageTile = 0, kStageSubgrid = 1, kStageImages = 2 };
 struct StagePlan {
@@ -88,17 +89,22 @@ struct StagePlan {
     // a one-stage noise plan (timed by the tuner) writes its coarse output
     // in sub-grid order for d = 2^cout_logd, as before a sub-grid stage
     int cout_logd = 0;
-    // first scale whose running statistics are in sub-grid order (0: none)
-    int subgrid_j0() const {
-        return nstages > 0 && st[nstages - 1].kind == kStageSubgrid ? st[nstages - 1].j0 : 0;
-    }
-    // first scale of the stage on sub-grid images (0: none)
-    int images_j0() const {
-        for (int k = 0; k < nstages; ++k)
-            if (st[k].kind == kStageImages) return st[k].j0;
-        return 0;
-    }
 };
+
+// Where a noise schedule leaves each scale's running statistics: from the
+// first scale j0[k] of its k-th stage on sub-grids (images or whole
+// sub-grids, in order) they are in the sub-grid order of d = 2^(j0[k]-1),
+// nested inside each sub-grid of the stage before (stat_index).
+struct StatLayout {
+    int count = 0;
+    int j0[8];
+};
+inline StatLayout stat_layout(const StagePlan* p) {
+    StatLayout l;
+    for (int k = 0; p && k < p->nstages && l.count < 8; ++k)
+        if (p->st[k].kind != kStageTile) l.j0[l.count++] = p->st[k].j0;
+    return l;
+}
 
 template <typename T>
 struct StarletArgs {
@@ -153,7 +159,7 @@ hipError_t launch_reconstruct(int logn, int J, const T* planes, T* out, hipStrea
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s,
-                                 int subgrid_j0 = 0, int images_j0 = 0);
+                                 const StatLayout& layout = StatLayout());
 hipError_t launch_zero_f64(double* p, long long count, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long count, hipStream_t s);
 

@@ -402,7 +402,7 @@ amap_status enqueue_noise(const amap_ctx* ctx, char* ws, int n, int J, const T* 
         AMAP_HIP(launch_starlet<T>(a), "noise starlet kernels");
     }
     AMAP_HIP(launch_noise_finalize<T>(logn, J, n_real, M2, planes_signal, sigma, snr, s,
-                                      plan ? plan->subgrid_j0() : 0, plan ? plan->images_j0() : 0),
+                                      stat_layout(plan)),
              "noise finalize");
     return AMAP_OK;
 }

@@ -680,7 +680,10 @@ k_starlet_noise_stage(NoiseStageArgs<T> a) {
     // column p, whole vectors of G consecutive sub-grid pixels; the owned
     // vector (row pv, index ix) then stands for vector xg = ix % per of
     // sub-grid column p = ix / per (per = tw / (G d)), gathered from LDS
-    // and stored whole.  Otherwise each value is stored on its own.
+    // and stored whole.  Otherwise each value is stored on its own.  (Going
+    // out sub-grid by sub-grid instead, so that a wavefront writes the rows
+    // of one or two sub-grids, measured 15% slower: its strided gathers
+    // from LDS conflict in the banks.)
     const int sgd = SG ? 1 << a.cout_logd : 0;
     const bool sg_vec = SG && g.tw % (G * sgd) == 0;
     // the tile row and tile-relative column of that vector's first pixel
@@ -1494,10 +1497,11 @@ bool plan_valid(int n, int J, bool noise, const StagePlan& plan) {
                 (t.rb != 1 && t.rb != 2) || t.tw != (n >> (t.j0 - 1)) || t.th != t.tw)
                 return false;
         } else if (t.kind == kStageImages) {
-            // after a plain tile stage; the last stage or followed by the final sub-grid stage
+            // after a plain tile stage or another such stage; the last stage or
+            // followed by another such stage or the final sub-grid stage
             StageGeom g{};
-            if (!noise || k == 0 || plan.st[k - 1].kind != kStageTile ||
-                (k + 1 < plan.nstages && plan.st[k + 1].kind != kStageSubgrid) || t.ns > 3 ||
+            if (!noise || k == 0 || plan.st[k - 1].kind == kStageSubgrid ||
+                (k + 1 < plan.nstages && plan.st[k + 1].kind == kStageTile) || t.ns > 3 ||
                 !images_geom<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, &g))
                 return false;
         } else if (t.kind == kStageTile) {
@@ -1539,8 +1543,8 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
                 continue;
             }
             if (t.kind == kStageImages) {  // noise tiles on sub-grid images
-                if (!acc || (k > 0 && a.plan->st[k - 1].kind != kStageTile) ||
-                    (k + 1 < a.plan->nstages && a.plan->st[k + 1].kind != kStageSubgrid) ||
+                if (!acc || (k > 0 && a.plan->st[k - 1].kind == kStageSubgrid) ||
+                    (k + 1 < a.plan->nstages && a.plan->st[k + 1].kind == kStageTile) ||
                     !images_geom<T>(n, t.j0, t.ns, t.tw, t.th, t.rb, &g))
                     return hipErrorInvalidValue;
                 plan[nstages++] = Stage{t.j0, t.ns, g, true, false, true};
@@ -1653,7 +1657,7 @@ hipError_t launch_starlet(const StarletArgs<T>& a) {
             s.img_logd = li;
             s.cout_logd = (gi + 1 < nstages && (plan[gi + 1].sub || plan[gi + 1].images))
                               ? plan[gi + 1].j0 - 1 - li
-                              : (a.plan && nstages == 1 && !st.images && dst ? a.plan->cout_logd : 0);
+                              : (a.plan && nstages == 1 && dst ? a.plan->cout_logd : 0);
             {
                 using AccT = typename std::conditional<sizeof(T) == 8, double, float>::type;
                 if (s.groups > 1 && (size_t)s.groups * st.ns * 2 * (size_t)n2 * sizeof(AccT) >
@@ -1795,17 +1799,19 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
     // best[j]: least time for scales j .. J-1 from c_{j-1} in natural order,
     // pick[j] its first stage, then_images[j] whether a stage on sub-grid
     // images follows it; img[j]: least time for scales j .. J-1 starting with
-    // a stage on sub-grid images (then the final sub-grid stage, if any
-    // scales are left), img_pick[j] that stage; sub[j]: the final sub-grid
-    // stage from j, sub_pick[j] it.
+    // a stage on sub-grid images, img_pick[j] that stage and img_next[j] what
+    // follows it (0 nothing, 1 the final sub-grid stage, 2 another stage on
+    // sub-grid images); sub[j]: the final sub-grid stage from j, sub_pick[j] it.
     float best[18], img[18], sub[18];
     StagePlan::Stage pick[18], img_pick[18], sub_pick[18];
     bool then_images[18];
+    int img_next[18];
     best[J] = 0.f;
     img[J] = sub[J] = -1.f;
     for (int j = J - 1; j >= 1 && e == hipSuccess; --j) {
         best[j] = img[j] = sub[j] = -1.f;
         then_images[j] = false;
+        img_next[j] = 0;
         for (int rb = 1; rb <= 2 && acc && e == hipSuccess && subgrid_ok<T>(n, j, J); ++rb) {
             // all remaining scales on whole sub-grids (a final stage)
             const int m = n >> (j - 1);
@@ -1819,17 +1825,24 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
         }
         // a tile stage on the sub-grid images of d0 = 2^(j-1)
         for (int ns = 1; ns <= 3 && acc && j >= 2 && j + ns <= J && (n >> (j - 1)) >= 16 && e == hipSuccess; ++ns) {
-            const float tail = j + ns == J ? 0.f : sub[j + ns];
+            // what follows: nothing, the final sub-grid stage or another images stage
+            float tail = j + ns == J ? 0.f : -1.f;
+            int next = 0;
+            if (j + ns < J) {
+                if (sub[j + ns] >= 0.f) { tail = sub[j + ns]; next = 1; }
+                if (img[j + ns] >= 0.f && (tail < 0.f || img[j + ns] < tail)) { tail = img[j + ns]; next = 2; }
+            }
             if (tail < 0.f) continue;
             StageGeom cand[24];
             const int nc = candidates(n >> (j - 1), 1, ns, cand);
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 const StagePlan::Stage st{j, ns, cand[c].tw, cand[c].th, cand[c].rb, kStageImages};
                 float t = 0.f;
-                e = time_stage(st, &t);
+                e = time_stage(st, &t, next ? j + ns - 1 - (j - 1) : 0);
                 if (e == hipSuccess && (img[j] < 0.f || t + tail < img[j])) {
                     img[j] = t + tail;
                     img_pick[j] = st;
+                    img_next[j] = next;
                 }
             }
         }
@@ -1868,11 +1881,12 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
         const bool to_img = then_images[j];
         out->st[out->nstages++] = pick[j];
         j += pick[j].ns;
-        if (to_img) {
+        while (to_img && j < J) {  // the chain of stages on sub-grid images
+            const int next = img_next[j];
             out->st[out->nstages++] = img_pick[j];
             j += img_pick[j].ns;
-            if (j < J) out->st[out->nstages++] = sub_pick[j];
-            break;
+            if (next == 1) out->st[out->nstages++] = sub_pick[j];
+            if (next != 2) j = J;
         }
     }
     return hipSuccess;

@@ -6,34 +6,32 @@
 
 namespace amap {
 
-// Where each scale's running statistics sit: scales from images_j0 on (0:
-// none) in sub-grid order for d1 = 2^(images_j0 - 1); scales from
-// subgrid_j0 on (0: none) in sub-grid order for d = 2^(subgrid_j0 - 1),
-// which after an images stage is that order within each d1 sub-grid.
-__device__ __forceinline__ long long stat_index(long long idx, int logn, int j, int subgrid_j0,
-                                                int images_j0) {
-    if (images_j0 > 0 && j >= images_j0) {
-        const int l1 = images_j0 - 1, lm = logn - l1;
-        long long s = subgrid_index(idx, logn, l1);
-        if (subgrid_j0 > 0 && j >= subgrid_j0) {
-            const long long mask = (1ll << (2 * lm)) - 1;
-            s = (s & ~mask) | subgrid_index(s & mask, lm, subgrid_j0 - 1 - l1);
-        }
-        return s;
+// Index of pixel idx's statistics for scale j under `lay`: for every stage
+// on sub-grids that has started by scale j, the pixel's place in the
+// current block (the whole plane, then one sub-grid of the stage before)
+// goes to that block's sub-grid order for the stage's d.
+__device__ __forceinline__ long long stat_index(long long idx, int logn, int j, const StatLayout& lay) {
+    long long s = idx;
+    int dprev = 0;
+    for (int k = 0; k < lay.count && lay.j0[k] <= j; ++k) {
+        const int d = lay.j0[k] - 1, lm = logn - dprev;
+        const long long mask = (1ll << (2 * lm)) - 1;
+        s = (s & ~mask) | subgrid_index(s & mask, lm, d - dprev);
+        dprev = d;
     }
-    return subgrid_j0 > 0 && j >= subgrid_j0 ? subgrid_index(idx, logn, subgrid_j0 - 1) : idx;
+    return s;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_noise_finalize(const double* __restrict__ M2, int R, int J, int logn, int subgrid_j0, int images_j0,
+k_noise_finalize(const double* __restrict__ M2, int R, int J, int logn, StatLayout lay,
                  const T* __restrict__ planes_signal, T* __restrict__ sigma, T* __restrict__ snr) {
     const long long n2 = 1ll << (2 * logn);
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= n2) return;
     for (int j = 0; j < J - 1; ++j) {
         const long long e = (long long)j * n2 + idx;
-        double var = M2[(long long)j * n2 + stat_index(idx, logn, j + 1, subgrid_j0, images_j0)] /
+        double var = M2[(long long)j * n2 + stat_index(idx, logn, j + 1, lay)] /
                      (double)(R - 1);
         var = var > 0.0 ? var : 0.0;
         const T sg = (T)sqrt(var);
@@ -249,13 +247,14 @@ static unsigned peak_blocks(long long n2) {
 template <typename T>
 hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s,
-                                 int subgrid_j0, int images_j0) {
+                                 const StatLayout& layout) {
     const long long n2 = 1ll << (2 * logn);
-    if (subgrid_j0 < 0 || subgrid_j0 >= J || images_j0 < 0 || images_j0 >= J ||
-        (images_j0 > 0 && subgrid_j0 > 0 && subgrid_j0 <= images_j0))
-        return hipErrorInvalidValue;
+    if (layout.count < 0 || layout.count > 8) return hipErrorInvalidValue;
+    for (int k = 0; k < layout.count; ++k)  // stage starts inside [1, J), increasing
+        if (layout.j0[k] < 1 || layout.j0[k] >= J || (k > 0 && layout.j0[k] <= layout.j0[k - 1]))
+            return hipErrorInvalidValue;
     AMAP_LAUNCH("noise_finalize", s,
-                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(M2, R, J, logn, subgrid_j0, images_j0,
+                k_noise_finalize<T><<<blocks_for(n2), 256, 0, s>>>(M2, R, J, logn, layout,
                                                                    planes_signal, sigma, snr));
     return hipGetLastError();
 }
@@ -319,9 +318,9 @@ hipError_t launch_phase_u32(int logn, uint64_t seed, uint64_t r, uint32_t* out, 
 }
 
 template hipError_t launch_noise_finalize<float>(int, int, int, const double*, const float*, float*,
-                                                 float*, hipStream_t, int, int);
+                                                 float*, hipStream_t, const StatLayout&);
 template hipError_t launch_noise_finalize<double>(int, int, int, const double*, const double*,
-                                                  double*, double*, hipStream_t, int, int);
+                                                  double*, double*, hipStream_t, const StatLayout&);
 template hipError_t launch_count_peaks<float>(int, int, const float*, double, long long*, hipStream_t);
 template hipError_t launch_count_peaks<double>(int, int, const double*, double, long long*, hipStream_t);
 template hipError_t launch_peak_hist<float>(int, int, const float*, int, double, double, int, long long*,

@@ -6,11 +6,15 @@ images of side n / d on which scale j0 + s has dilation 2^s.  A stage of
 kind 2 takes the previous stage's coarse plane in that sub-grid order and
 runs the ordinary noise tile stage on every image: its x halo is that of a
 first stage instead of growing with d.  It is the last stage or is followed
-by the final sub-grid stage, whose sub-grids it lays out image by image; the
-finalize kernel maps each scale's statistics back to pixel order.
+by another such stage or the final sub-grid stage, whose sub-grids it lays
+out image by image; the finalize kernel maps each scale's statistics back
+to pixel order.
 
-Schedules with such stages are loaded explicitly (amap_plans_load, keyed by
-the batch the call runs) and checked against the FP64 oracle: sigma within
+Such stages can follow one another: each takes the sub-grids of its own d
+as images, laid out inside the sub-grids of the stage before (nested
+sub-grid orders).  Schedules with such stages are loaded explicitly
+(amap_plans_load, keyed by the batch the call runs) and checked against
+the FP64 oracle: sigma within
 1e-5 * rms(kappa) (1e-10 for float64), against the analytic tile-only
 schedule to rounding, S/N by the propagated bound and peak counts bit-exact
 on identical planes.  Capped batches cover the cross-batch merge of these
@@ -39,6 +43,15 @@ CASES = [
     (512, 7, 5, torch.float32, 2, [[1, 2, 64, 32, 1, 0], [3, 1, 64, 32, 1, 2], [4, 3, 64, 64, 1, 1]]),
     (256, 6, 4, torch.float64, 0, [[1, 2, 32, 32, 1, 0], [3, 2, 32, 32, 1, 2], [5, 1, 16, 16, 1, 1]]),
     (128, 5, 5, torch.float64, 2, [[1, 1, 32, 16, 1, 0], [2, 2, 32, 16, 1, 2], [4, 1, 16, 16, 1, 1]]),
+    # chains of stages on sub-grid images (nested sub-grid orders)
+    (1024, 8, 6, torch.float32, 0, [[1, 1, 64, 32, 1, 0], [2, 2, 64, 32, 1, 2], [4, 2, 32, 32, 1, 2],
+                                    [6, 2, 32, 32, 1, 2]]),
+    (1024, 8, 5, torch.float32, 3, [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 2], [5, 2, 64, 32, 2, 2],
+                                    [7, 1, 16, 16, 2, 1]]),
+    (2048, 8, 3, torch.float32, 0, [[1, 2, 64, 32, 1, 0], [3, 1, 64, 32, 1, 2], [4, 2, 64, 32, 1, 2],
+                                    [6, 2, 64, 64, 1, 1]]),
+    (256, 7, 4, torch.float64, 0, [[1, 2, 32, 32, 1, 0], [3, 1, 32, 32, 1, 2], [4, 1, 32, 32, 1, 2],
+                                   [5, 2, 16, 16, 1, 1]]),
 ]
 
 
@@ -117,7 +130,7 @@ def test_image_stage_schedules_are_validated():
     bad = [
         [[1, 2, 64, 32, 2, 2], [3, 2, 64, 32, 2, 0], [5, 2, 64, 64, 2, 1]],   # images stage first
         [[1, 2, 64, 32, 2, 0], [3, 1, 64, 32, 2, 2], [4, 1, 64, 32, 2, 0], [5, 2, 64, 64, 2, 1]],  # then a tile stage
-        [[1, 2, 64, 32, 2, 0], [3, 1, 64, 32, 2, 2], [4, 1, 64, 32, 2, 2], [5, 2, 64, 64, 2, 1]],  # two in a row
+        [[1, 2, 64, 32, 2, 0], [3, 2, 64, 64, 2, 1], [5, 2, 64, 32, 2, 2]],   # after the sub-grid stage
         [[1, 2, 64, 32, 2, 0], [3, 2, 48, 32, 2, 2], [5, 2, 64, 64, 2, 1]],   # no such tile
         [[1, 2, 64, 32, 2, 0], [3, 2, 64, 32, 2, 3], [5, 2, 64, 64, 2, 1]],   # no such kind
     ]
