@@ -97,11 +97,11 @@ struct StagePlan {
 // nested inside each sub-grid of the stage before (stat_index).
 struct StatLayout {
     int count = 0;
-    int j0[8];
+    int j0[16];  // as many as a schedule has stages
 };
 inline StatLayout stat_layout(const StagePlan* p) {
     StatLayout l;
-    for (int k = 0; p && k < p->nstages && l.count < 8; ++k)
+    for (int k = 0; p && k < p->nstages && l.count < 16; ++k)
         if (p->st[k].kind != kStageTile) l.j0[l.count++] = p->st[k].j0;
     return l;
 }

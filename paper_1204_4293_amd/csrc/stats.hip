@@ -249,7 +249,7 @@ hipError_t launch_noise_finalize(int logn, int J, int R, const double* M2,
                                  const T* planes_signal, T* sigma, T* snr, hipStream_t s,
                                  const StatLayout& layout) {
     const long long n2 = 1ll << (2 * logn);
-    if (layout.count < 0 || layout.count > 8) return hipErrorInvalidValue;
+    if (layout.count < 0 || layout.count > 16) return hipErrorInvalidValue;
     for (int k = 0; k < layout.count; ++k)  // stage starts inside [1, J), increasing
         if (layout.j0[k] < 1 || layout.j0[k] >= J || (k > 0 && layout.j0[k] <= layout.j0[k - 1]))
             return hipErrorInvalidValue;
