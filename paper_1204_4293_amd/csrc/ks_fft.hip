@@ -19,8 +19,8 @@
 // LDS exchange separates the two steps.  Along x a transform's N2 threads
 // sit in one wavefront, so the exchange needs no workgroup barrier, and the
 // inverse transform starts from the forward output exactly as each thread
-// holds it.  Sides whose per-thread DFTs would not fit in registers (float32
-// from 2048, float64 from 1024) use radix-4 Stockham passes held in LDS.
+// holds it.  Float64 from 1024 points, whose per-thread DFTs would not fit
+// the register file, uses radix-4 Stockham passes held in LDS instead.
 #include "amap_device.h"
 #include "amap_launch.h"
 #include "fft_reg.h"

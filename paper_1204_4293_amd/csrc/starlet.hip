@@ -18,6 +18,12 @@
 // bounded halo overhead; scales whose dilation leaves no such tile use
 // per-scale row and column kernels.
 //
+// Noise statistics have two more stage kinds, for the coarse scales: tile
+// stages on the periodic sub-grid images of d0 (from scale j0 every tap
+// joins pixels congruent mod d0, so each sub-grid is a map of its own with
+// the dilations of a first stage), and a final stage on whole sub-grids
+// held in LDS.
+//
 // Maps (or noise realisations) are spread over gridDim.y.  For noise maps the
 // stages keep a running mean and sum of squared deviations per pixel
 // (Welford's update over the batch, then Chan, Golub & LeVeque's pairwise
