@@ -125,9 +125,10 @@ amap_status amap_set_autotune(amap_ctx_t ctx, int enable);
  * final stage on whole sub-grids, one per workgroup (width and sub-rows are
  * the sub-grid side); kind 2 (noise statistics): a tile stage on the
  * sub-grids of d taken as images, with the tile of an (n/d) x (n/d) map's
- * first stage; it follows a kind-0 stage and is the last stage or followed
- * by a kind-1 stage.  An empty stage list means the analytic planner is
- * used for that shape.
+ * first stage; it follows a kind-0 or kind-2 stage and is the last stage or
+ * followed by a kind-2 or kind-1 stage (each such stage lays out the
+ * sub-grids of the next inside its own images).  An empty stage list means
+ * the analytic planner is used for that shape.
  * AMAP_E_INVAL if it does not fit. */
 amap_status amap_plans_read(amap_ctx_t ctx, char* buf, size_t len);
 
