@@ -105,8 +105,7 @@ constexpr int bc_max_d() { return sizeof(T) == 4 ? 128 : 64; }
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bc_scale_tile(const T* __restrict__ c_prev, T* __restrict__ w, T* __restrict__ c_next, int ny,
-                int nx, int d, int mode, int row_tiles, long long cp_stride, long long cn_stride,
-                long long w_stride) {
+                int nx, int d, int mode, long long cp_stride, long long cn_stride, long long w_stride) {
     extern __shared__ unsigned char lds_raw[];
     T* reg = reinterpret_cast<T*>(lds_raw);            // [kBcTH + 4][RW]
     const int RW = kBcTW + 4 * d;
@@ -377,8 +376,8 @@ hipError_t launch_starlet_bc(int ny, int nx, int J, int mode, const T* image, T*
         const size_t lds = (size_t)(kBcTH + 4) * (kBcTW + 4 * d + kBcTW) * sizeof(T);
         AMAP_LAUNCH("starlet_bc_tile", s,
                     k_bc_scale_tile<T><<<grid, 256, lds, s>>>(c_prev, planes + (long long)(j - 1) * plane,
-                                                              dst, ny, nx, d, mode, row_tiles, cp_stride,
-                                                              dst_stride, planes_stride));
+                                                              dst, ny, nx, d, mode, cp_stride, dst_stride,
+                                                              planes_stride));
         c_prev = dst;
         cp_stride = dst_stride;
     }

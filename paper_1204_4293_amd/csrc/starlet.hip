@@ -155,7 +155,6 @@ __host__ __device__ inline int stage_hx(int d0, int ns, int G) {
 
 constexpr int kSegLen = 4;        // column-pass outputs per sliding window
 constexpr int kVecPerThread = 2;  // owned output vectors per thread
-constexpr int kPrefetch = 6;      // tile vectors per thread held while prefetching
 
 // Noise stages: NT threads, each owning KV output vectors (its Welford state
 // lives in registers).  Tiles of up to 1024 vectors run one vector per
@@ -173,7 +172,7 @@ __host__ __device__ constexpr NoiseCfg noise_cfg(int vec) {
 // vectors may not exceed nt times this.  One-vector stages keep 3 (their
 // 128-register budget), or 2 when two realisations are processed at a time;
 // four-vector stages hold 8.
-__host__ __device__ constexpr int noise_prefetch(int nt, int kv, int rb = 1) {
+__host__ __device__ constexpr int noise_prefetch(int /*nt*/, int kv, int rb = 1) {
     return kv > 1 ? 8 : (rb > 1 ? 2 : 3);
 }
 
@@ -1844,7 +1843,7 @@ hipError_t tune_starlet(const StarletArgs<T>& a, int reps, StagePlan* out) {
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 const StagePlan::Stage st{j, ns, cand[c].tw, cand[c].th, cand[c].rb, kStageImages};
                 float t = 0.f;
-                e = time_stage(st, &t, next ? j + ns - 1 - (j - 1) : 0);
+                e = time_stage(st, &t, next ? ns : 0);  // the next stage's d over this one's
                 if (e == hipSuccess && (img[j] < 0.f || t + tail < img[j])) {
                     img[j] = t + tail;
                     img_pick[j] = st;
