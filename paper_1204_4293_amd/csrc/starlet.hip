@@ -11,8 +11,8 @@
 // the rows stay contiguous so every HBM access is a long row segment.  The
 // tile carries a halo of 2 d0 (2^ns - 1) pixels along x and 2 (2^ns - 1)
 // sub-rows along y.  Two LDS buffers: the row pass reads A and writes B, the
-// column pass reads B and writes A, one barrier after each; wavefronts take
-// rows and lanes take pixels, so no index is divided.  Each thread keeps
+// column pass reads B and writes A, one barrier after each; the column pass
+// slides a window of five rows down each vector column.  Each thread keeps
 // c_{j-1} of its own output pixels in registers to form w_j.  The host picks
 // per stage the largest scale count whose tile fits twice in LDS with a
 // bounded halo overhead; scales whose dilation leaves no such tile use
